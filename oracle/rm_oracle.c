@@ -1,0 +1,852 @@
+/*
+ * rm_oracle.c -- TEST INFRASTRUCTURE, not product code.
+ *
+ * Plain CPU oracle for the permuted FHT-FSCL decoder of Reed-Muller codes
+ * (Doan, Hashemi, Gross, arXiv 2108.12550).  It is written to be read next to
+ * the paper: every function follows one passage and keeps its order of steps.
+ * Only tests/, __graft_entry__.smoke() and bench.py's cpu_baseline leg may
+ * load it; it shares nothing with the HIP decoder.
+ *
+ * Arithmetic is scalar IEEE binary32 (the decoder's working precision), built
+ * with -O2 -ffp-contract=off and no fast-math, so that every decision (sorts,
+ * arg-max, hard decisions) is taken on the same values as a GPU path that
+ * follows the same operation order.  Where the paper leaves an order or a tie
+ * open, the choice made here is stated in a comment and listed as a reading.
+ */
+#include "rm_oracle.h"
+
+#include <math.h>
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define MAXM 10          /* N <= 1024 */
+#define MAXL 64
+
+/* ------------------------------------------------------------------------ */
+/* SplitMix64, from its published definition (Steele, Lea and Flood,        */
+/* "Fast splittable pseudorandom number generators", OOPSLA 2014): a Weyl    */
+/* sequence with increment 0x9E3779B97F4A7C15 passed through a 64-bit mix.    */
+/* ------------------------------------------------------------------------ */
+uint64_t rmo_splitmix64_next(uint64_t *state)
+{
+    uint64_t z = (*state += 0x9E3779B97F4A7C15ULL);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Affine maps z -> A z + b over F2^m (the full symmetry group of RM(r,m)   */
+/* for 1 <= r <= m-2).  Position i is the point z(i) with z_k = bit k of i.  */
+/* Row j of A gives output bit j: (A z)_j = parity(row_j & i).               */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int m;
+    uint32_t row[MAXM];
+    uint32_t b;
+} amap;
+
+static int parity32(uint32_t v)
+{
+    int p = 0;
+    while (v) {
+        p ^= 1;
+        v &= v - 1;
+    }
+    return p;
+}
+
+static uint32_t amap_apply(const amap *a, uint32_t i)
+{
+    uint32_t z = 0;
+    for (int j = 0; j < a->m; j++)
+        z |= (uint32_t)parity32(a->row[j] & i) << j;
+    return z ^ a->b;
+}
+
+/* Gaussian elimination over GF(2). */
+static int gf2_full_rank(const uint32_t *rows, int m)
+{
+    uint32_t t[MAXM];
+    memcpy(t, rows, (size_t)m * sizeof *t);
+    int rank = 0;
+    for (int col = 0; col < m; col++) {
+        int piv = -1;
+        for (int k = rank; k < m; k++)
+            if ((t[k] >> col) & 1u) {
+                piv = k;
+                break;
+            }
+        if (piv < 0)
+            continue;
+        uint32_t tmp = t[piv];
+        t[piv] = t[rank];
+        t[rank] = tmp;
+        for (int k = 0; k < m; k++)
+            if (k != rank && ((t[k] >> col) & 1u))
+                t[k] ^= t[rank];
+        rank++;
+    }
+    return rank == m;
+}
+
+/* One uniform element of AGL(m,2): draw the m rows of A (low m bits of one
+ * SplitMix64 output each) until A is invertible, then draw b. */
+static void amap_draw(amap *a, int m, uint64_t *st)
+{
+    const uint32_t mask = (1u << m) - 1u;
+    a->m = m;
+    do {
+        for (int k = 0; k < m; k++)
+            a->row[k] = (uint32_t)(rmo_splitmix64_next(st) & mask);
+    } while (!gf2_full_rank(a->row, m));
+    a->b = (uint32_t)(rmo_splitmix64_next(st) & mask);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Code construction (Section II-A): x = u G^{(x)m}, G = [[1,0],[1,1]];      */
+/* u_i is frozen iff the weight w_i of row i of G^{(x)m} is below            */
+/* d = 2^{m-r}.  The Kronecker powers are built explicitly.                  */
+/* ------------------------------------------------------------------------ */
+static uint8_t *gkron[MAXM + 1];
+static pthread_mutex_t gkron_lock = PTHREAD_MUTEX_INITIALIZER;
+
+static const uint8_t *kron_power(int s)
+{
+    pthread_mutex_lock(&gkron_lock);
+    if (!gkron[0]) {
+        gkron[0] = malloc(1);
+        gkron[0][0] = 1;
+        for (int t = 1; t <= MAXM; t++) {
+            int n = 1 << t, h = n / 2;
+            uint8_t *g = calloc((size_t)n * n, 1);
+            const uint8_t *p = gkron[t - 1];
+            /* G (x) P = [[P, 0], [P, P]] */
+            for (int i = 0; i < h; i++)
+                for (int j = 0; j < h; j++) {
+                    g[(size_t)i * n + j] = p[(size_t)i * h + j];
+                    g[(size_t)(i + h) * n + j] = p[(size_t)i * h + j];
+                    g[(size_t)(i + h) * n + j + h] = p[(size_t)i * h + j];
+                }
+            gkron[t] = g;
+        }
+    }
+    pthread_mutex_unlock(&gkron_lock);
+    return gkron[s];
+}
+
+int rmo_info_set(int m, int r, uint8_t *is_info)
+{
+    if (m < 0 || m > MAXM || r < 0 || r > m)
+        return -1;
+    const int n = 1 << m;
+    const uint8_t *g = kron_power(m);
+    const long d = 1L << (m - r);
+    for (int i = 0; i < n; i++) {
+        long w = 0;
+        for (int j = 0; j < n; j++)
+            w += g[(size_t)i * n + j];
+        is_info[i] = (uint8_t)(w >= d);
+    }
+    return 0;
+}
+
+int rmo_encode(int m, const uint8_t *u, uint8_t *x)
+{
+    if (m < 0 || m > MAXM)
+        return -1;
+    const int n = 1 << m;
+    const uint8_t *g = kron_power(m);
+    for (int j = 0; j < n; j++)
+        x[j] = 0;
+    for (int k = 0; k < n; k++)
+        if (u[k])
+            for (int j = 0; j < n; j++)
+                x[j] ^= g[(size_t)k * n + j];
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Processing element (Section II-B), min-sum form.                          */
+/* ------------------------------------------------------------------------ */
+static float sgnf(float a) { return a < 0.0f ? -1.0f : 1.0f; } /* sgn(0) reads +1 */
+
+static float f_minsum(float a, float b) { return sgnf(a) * sgnf(b) * fminf(fabsf(a), fabsf(b)); }
+
+static float g_func(float a, float b, uint8_t c) { return b + (1.0f - 2.0f * (float)c) * a; }
+
+/* Sum of n values by the halving tree v[i] += v[i+w], w = n/2, n/4, ..., 1.
+ * The paper fixes no summation order; this one is the decoder's contract. */
+static float tree_sum(const float *v, int n)
+{
+    float *t = malloc((size_t)n * sizeof *t);
+    memcpy(t, v, (size_t)n * sizeof *t);
+    for (int w = n / 2; w >= 1; w /= 2)
+        for (int i = 0; i < w; i++)
+            t[i] = t[i] + t[i + w];
+    float s = t[0];
+    free(t);
+    return s;
+}
+
+/* Stable ascending insertion sort of the index array ord[] by key[]. */
+static void stable_sort_asc(int *ord, const float *key, int n)
+{
+    for (int a = 1; a < n; a++) {
+        int v = ord[a], b = a - 1;
+        while (b >= 0 && key[ord[b]] > key[v]) {
+            ord[b + 1] = ord[b];
+            b--;
+        }
+        ord[b + 1] = v;
+    }
+}
+
+/* Stable descending insertion sort of ord[] by key[]. */
+static void stable_sort_desc(int *ord, const float *key, int n)
+{
+    for (int a = 1; a < n; a++) {
+        int v = ord[a], b = a - 1;
+        while (b >= 0 && key[ord[b]] < key[v]) {
+            ord[b + 1] = ord[b];
+            b--;
+        }
+        ord[b + 1] = v;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Alg. 4: FHT decoding of one path of a first-order node RM(1,s), with the  */
+/* low-cost path metric of Eq. (10).  Returns k = min(L, 2^s) candidates:    */
+/* codewords cw[j*n..], metrics pm[j] and the transform index idx[j].        */
+/* ------------------------------------------------------------------------ */
+int rmo_fht(int s, int L, const float *alpha, float pm_in, uint8_t *cw, float *pm, int *idx)
+{
+    if (s < 1 || s > MAXM || L < 1)
+        return -1;
+    const int n = 1 << s;
+    const int k = L < n ? L : n;
+    float *F = malloc((size_t)n * sizeof *F);
+    float *ab = malloc((size_t)n * sizeof *ab);
+    uint8_t *taken = calloc((size_t)n, 1);
+    uint8_t *info = malloc((size_t)n);
+    uint8_t *u = malloc((size_t)n);
+    rmo_info_set(s, 1, info);
+
+    /* Initialisation: working copy and LLR_abs = sum of |alpha|. */
+    for (int i = 0; i < n; i++) {
+        F[i] = alpha[i];
+        ab[i] = fabsf(alpha[i]);
+    }
+    const float llr_abs = tree_sum(ab, n);
+
+    /* In-place butterflies, stride 2^{s-t-1} for t = 0..s-1; 2^t blocks of
+     * width 2^{s-t} (the block loop bound of the listing is read as j < 2^t). */
+    for (int t = 0; t < s; t++) {
+        const int h = 1 << (s - t - 1);
+        for (int j = 0; j < (1 << t); j++)
+            for (int i = j * 2 * h; i < j * 2 * h + h; i++) {
+                const float a = F[i + h] - F[i];
+                const float b = F[i + h] + F[i];
+                F[i] = a;
+                F[i + h] = b;
+            }
+    }
+
+    /* Up to L best entries of |F|: L passes that each take the largest entry
+     * not yet taken (ties go to the lower index), as the text describes. */
+    for (int j = 0; j < k; j++) {
+        int best = -1;
+        for (int i = 0; i < n; i++)
+            if (!taken[i] && (best < 0 || fabsf(F[i]) > fabsf(F[best])))
+                best = i;
+        taken[best] = 1;
+        idx[j] = best;
+    }
+
+    for (int j = 0; j < k; j++) {
+        const int is = idx[j];
+        uint8_t msg[MAXM + 1];
+        msg[s] = (uint8_t)(F[is] < 0.0f);          /* m_s from the sign */
+        const unsigned c = (unsigned)(n - 1 - is); /* dec2bin(2^s - 1 - i*) */
+        /* {m_{s-1}, ..., m_0} lists the binary digits of c least significant
+         * first, i.e. m_t is bit s-1-t of c. */
+        for (int t = 0; t < s; t++)
+            msg[t] = (uint8_t)((c >> (s - 1 - t)) & 1u);
+        int t = 0;
+        for (int kk = 0; kk < n; kk++) {
+            u[kk] = 0;
+            if (info[kk])
+                u[kk] = msg[t++];
+        }
+        rmo_encode(s, u, cw + (size_t)j * n);
+        pm[j] = pm_in + 0.5f * (llr_abs - fabsf(F[is]));
+    }
+    free(F);
+    free(ab);
+    free(taken);
+    free(info);
+    free(u);
+    return k;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Alg. 3: FHTL.  Every path contributes min(L,2^s) candidates to E, listed  */
+/* path by path; E is sorted stably by metric (merge sort in the paper) and  */
+/* the first L survive.  anc[l] is the input path of survivor l.             */
+/* ------------------------------------------------------------------------ */
+static void fhtl_node(int s, int L, float *const *alpha, const float *pm_in, uint8_t **x, float *pm_out,
+                      int *anc)
+{
+    const int n = 1 << s;
+    const int k = L < n ? L : n;
+    const int ne = L * k;
+    uint8_t *cw = malloc((size_t)ne * n);
+    float *pe = malloc((size_t)ne * sizeof *pe);
+    int *src = malloc((size_t)ne * sizeof *src);
+    int *ord = malloc((size_t)ne * sizeof *ord);
+    int idx[MAXL];
+    for (int l = 0; l < L; l++) {
+        rmo_fht(s, L, alpha[l], pm_in[l], cw + (size_t)l * k * n, pe + (size_t)l * k, idx);
+        for (int j = 0; j < k; j++)
+            src[l * k + j] = l;
+    }
+    for (int e = 0; e < ne; e++)
+        ord[e] = e;
+    stable_sort_asc(ord, pe, ne);
+    for (int l = 0; l < L; l++) {
+        memcpy(x[l], cw + (size_t)ord[l] * n, (size_t)n);
+        pm_out[l] = pe[ord[l]];
+        anc[l] = src[ord[l]];
+    }
+    free(cw);
+    free(pe);
+    free(src);
+    free(ord);
+}
+
+int rmo_fhtl(int s, int L, const float *alpha, const float *pm_in, uint8_t *x, float *pm, int *anc)
+{
+    if (s < 1 || s > MAXM || L < 1 || L > MAXL)
+        return -1;
+    const int n = 1 << s;
+    float *ap[MAXL];
+    uint8_t *xp[MAXL];
+    for (int l = 0; l < L; l++) {
+        ap[l] = (float *)alpha + (size_t)l * n;
+        xp[l] = x + (size_t)l * n;
+    }
+    fhtl_node(s, L, ap, pm_in, xp, pm, anc);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* SPCL: fast list decoding of a single-parity-check node RM(s-1,s),         */
+/* Eqs. (2)-(6).  Per path: hard decisions, parity p, the least reliable      */
+/* positions o_0, o_1, ... (|alpha| ascending, ties to the lower index) and   */
+/* PM += |alpha_{o_0}| when p = 1.  Then tau splits on o_1..o_tau; each path  */
+/* is listed as (keep, flip), the list is sorted stably by metric and cut to  */
+/* L.  Last, o_0 is set so that the parity check holds.                       */
+/* tau = min(L, 2^s - 1), and tau = 0 for L = 1 (a split there can never win). */
+/* ------------------------------------------------------------------------ */
+static void spcl_node(int s, int L, float *const *alpha, const float *pm_in, uint8_t **x, float *pm_out,
+                      int *anc)
+{
+    const int n = 1 << s;
+    const int tau = (L == 1) ? 0 : (L < n - 1 ? L : n - 1);
+    int *order = malloc((size_t)L * (tau + 1) * sizeof *order);
+    uint8_t *hd = malloc((size_t)L * n);
+    uint8_t *taken = malloc((size_t)n);
+    /* path list: source path, hard decisions, parity, metric */
+    int *csrc = malloc((size_t)2 * L * sizeof *csrc);
+    uint8_t *ch = malloc((size_t)2 * L * n);
+    int *cp = malloc((size_t)2 * L * sizeof *cp);
+    float *cpm = malloc((size_t)2 * L * sizeof *cpm);
+    int *nsrc = malloc((size_t)2 * L * sizeof *nsrc);
+    uint8_t *nh = malloc((size_t)2 * L * n);
+    int *np = malloc((size_t)2 * L * sizeof *np);
+    float *npm = malloc((size_t)2 * L * sizeof *npm);
+    int *ord = malloc((size_t)2 * L * sizeof *ord);
+
+    for (int l = 0; l < L; l++) {
+        int p = 0;
+        for (int i = 0; i < n; i++) {
+            hd[(size_t)l * n + i] = (uint8_t)(alpha[l][i] < 0.0f); /* Eq. (2) */
+            p ^= hd[(size_t)l * n + i];
+        }
+        memset(taken, 0, (size_t)n);
+        for (int t = 0; t <= tau; t++) {
+            int best = -1;
+            for (int i = 0; i < n; i++)
+                if (!taken[i] && (best < 0 || fabsf(alpha[l][i]) < fabsf(alpha[l][best])))
+                    best = i;
+            taken[best] = 1;
+            order[l * (tau + 1) + t] = best;
+        }
+        csrc[l] = l;
+        memcpy(ch + (size_t)l * n, hd + (size_t)l * n, (size_t)n);
+        cp[l] = p;
+        cpm[l] = pm_in[l];
+        if (p) /* Eq. (3) */
+            cpm[l] = pm_in[l] + fabsf(alpha[l][order[l * (tau + 1)]]);
+    }
+
+    for (int t = 1; t <= tau; t++) {
+        for (int q = 0; q < L; q++) {
+            const int sp = csrc[q];
+            const int ot = order[sp * (tau + 1) + t];
+            const int o0 = order[sp * (tau + 1)];
+            /* keep */
+            nsrc[2 * q] = sp;
+            memcpy(nh + (size_t)(2 * q) * n, ch + (size_t)q * n, (size_t)n);
+            np[2 * q] = cp[q];
+            npm[2 * q] = cpm[q];
+            /* flip o_t: Eq. (4) with the path's current parity, then Eq. (5) */
+            nsrc[2 * q + 1] = sp;
+            memcpy(nh + (size_t)(2 * q + 1) * n, ch + (size_t)q * n, (size_t)n);
+            nh[(size_t)(2 * q + 1) * n + ot] ^= 1;
+            npm[2 * q + 1] = (cpm[q] + fabsf(alpha[sp][ot])) + (1.0f - 2.0f * (float)cp[q]) * fabsf(alpha[sp][o0]);
+            np[2 * q + 1] = cp[q] ^ 1;
+        }
+        for (int e = 0; e < 2 * L; e++)
+            ord[e] = e;
+        stable_sort_asc(ord, npm, 2 * L);
+        for (int q = 0; q < L; q++) {
+            const int e = ord[q];
+            csrc[q] = nsrc[e];
+            memcpy(ch + (size_t)q * n, nh + (size_t)e * n, (size_t)n);
+            cp[q] = np[e];
+            cpm[q] = npm[e];
+        }
+    }
+
+    for (int q = 0; q < L; q++) {
+        const int o0 = order[csrc[q] * (tau + 1)];
+        uint8_t *h = ch + (size_t)q * n;
+        int par = 0;
+        for (int i = 0; i < n; i++)
+            if (i != o0)
+                par ^= h[i];
+        h[o0] = (uint8_t)par; /* Eq. (6) */
+        memcpy(x[q], h, (size_t)n);
+        pm_out[q] = cpm[q];
+        anc[q] = csrc[q];
+    }
+    free(order);
+    free(hd);
+    free(taken);
+    free(csrc);
+    free(ch);
+    free(cp);
+    free(cpm);
+    free(nsrc);
+    free(nh);
+    free(np);
+    free(npm);
+    free(ord);
+}
+
+int rmo_spcl(int s, int L, const float *alpha, const float *pm_in, uint8_t *x, float *pm, int *anc)
+{
+    if (s < 1 || s > MAXM || L < 1 || L > MAXL)
+        return -1;
+    const int n = 1 << s;
+    float *ap[MAXL];
+    uint8_t *xp[MAXL];
+    for (int l = 0; l < L; l++) {
+        ap[l] = (float *)alpha + (size_t)l * n;
+        xp[l] = x + (size_t)l * n;
+    }
+    spcl_node(s, L, ap, pm_in, xp, pm, anc);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Decoder object: code parameters and the random permutations, drawn once  */
+/* from the seed in a fixed order: for each decoder d, the L initial maps,   */
+/* then 2L candidate maps for every permutation-domain node in preorder.     */
+/* ------------------------------------------------------------------------ */
+struct rmo_decoder {
+    int m, r, P, L, mode;
+    int n_perm_nodes; /* internal nodes visited while isPermutation holds */
+    amap *init;       /* [P][L] */
+    amap *cand;       /* [P][n_perm_nodes][2L] */
+};
+
+/* The permutation domain covers the internal nodes reached from the root by
+ * left steps before the first first-order node (Alg. 2: isPermutation is set
+ * at the root and cleared at the first r = 1 node, which is the leftmost). */
+static int count_perm_nodes(int m, int r, int mode)
+{
+    if (mode != RMO_PERM_PFHT)
+        return 0;
+    int c = 0;
+    while (1 < r && r < m - 1) {
+        c++;
+        r--;
+        m--;
+    }
+    return c;
+}
+
+rmo_decoder *rmo_create(int m, int r, int P, int L, int perm_mode, uint64_t seed)
+{
+    if (m < 2 || m > MAXM || r < 1 || r > m - 1 || P < 1 || L < 1 || L > MAXL)
+        return NULL;
+    if (perm_mode != RMO_PERM_NONE && perm_mode != RMO_PERM_PFHT)
+        return NULL;
+    /* Without permutations the L paths would start as L copies of one path;
+     * the single-active-path start of plain FHT-FSCL is not modelled here. */
+    if (perm_mode == RMO_PERM_NONE && L != 1)
+        return NULL;
+    rmo_decoder *d = calloc(1, sizeof *d);
+    d->m = m;
+    d->r = r;
+    d->P = P;
+    d->L = L;
+    d->mode = perm_mode;
+    d->n_perm_nodes = count_perm_nodes(m, r, perm_mode);
+    d->init = calloc((size_t)P * L, sizeof *d->init);
+    d->cand = calloc((size_t)P * (d->n_perm_nodes ? d->n_perm_nodes : 1) * 2 * L, sizeof *d->cand);
+    kron_power(0);
+    uint64_t st = seed;
+    for (int p = 0; p < P; p++) {
+        for (int l = 0; l < L; l++) {
+            amap *a = &d->init[(size_t)p * L + l];
+            if (perm_mode == RMO_PERM_PFHT) {
+                amap_draw(a, m, &st);
+            } else { /* identity */
+                a->m = m;
+                for (int k = 0; k < m; k++)
+                    a->row[k] = 1u << k;
+                a->b = 0;
+            }
+        }
+        for (int v = 0; v < d->n_perm_nodes; v++)
+            for (int c = 0; c < 2 * L; c++)
+                amap_draw(&d->cand[((size_t)p * d->n_perm_nodes + v) * 2 * L + c], m - v, &st);
+    }
+    return d;
+}
+
+void rmo_destroy(rmo_decoder *d)
+{
+    if (!d)
+        return;
+    free(d->init);
+    free(d->cand);
+    free(d);
+}
+
+int rmo_perm_count(const rmo_decoder *d) { return d->P * (d->L + d->n_perm_nodes * 2 * d->L); }
+
+int rmo_perm_export(const rmo_decoder *d, uint16_t *rows, uint16_t *b, int *mdim, int cap)
+{
+    int k = 0;
+    for (int p = 0; p < d->P; p++) {
+        for (int l = 0; l < d->L; l++) {
+            const amap *a = &d->init[(size_t)p * d->L + l];
+            if (k >= cap)
+                return -1;
+            for (int j = 0; j < 16; j++)
+                rows[k * 16 + j] = (uint16_t)(j < a->m ? a->row[j] : 0);
+            b[k] = (uint16_t)a->b;
+            mdim[k] = a->m;
+            k++;
+        }
+        for (int v = 0; v < d->n_perm_nodes; v++)
+            for (int c = 0; c < 2 * d->L; c++) {
+                const amap *a = &d->cand[((size_t)p * d->n_perm_nodes + v) * 2 * d->L + c];
+                if (k >= cap)
+                    return -1;
+                for (int j = 0; j < 16; j++)
+                    rows[k * 16 + j] = (uint16_t)(j < a->m ? a->row[j] : 0);
+                b[k] = (uint16_t)a->b;
+                mdim[k] = a->m;
+                k++;
+            }
+    }
+    return k;
+}
+
+/* Preorder node list as (kind, r, m) triples, following Alg. 2's tests in
+ * their order: 1<r<m-1 internal, then r=1 FHTL, then r=m-1 SPCL. */
+static int sched_walk(int m, int r, int *is_perm, int *out, int cap, int k)
+{
+    if (1 < r && r < m - 1) {
+        if (k + 3 <= cap) {
+            out[k] = *is_perm ? RMO_NODE_PERM : RMO_NODE_INTERNAL;
+            out[k + 1] = r;
+            out[k + 2] = m;
+        }
+        k += 3;
+        k = sched_walk(m - 1, r - 1, is_perm, out, cap, k);
+        k = sched_walk(m - 1, r, is_perm, out, cap, k);
+    } else if (r == 1) {
+        *is_perm = 0;
+        if (k + 3 <= cap) {
+            out[k] = RMO_NODE_FHTL;
+            out[k + 1] = r;
+            out[k + 2] = m;
+        }
+        k += 3;
+    } else if (r == m - 1) {
+        if (k + 3 <= cap) {
+            out[k] = RMO_NODE_SPCL;
+            out[k + 1] = r;
+            out[k + 2] = m;
+        }
+        k += 3;
+    }
+    return k;
+}
+
+int rmo_schedule(int m, int r, int perm_mode, int *out, int cap)
+{
+    if (m < 2 || m > MAXM || r < 1 || r > m - 1)
+        return -1;
+    int is_perm = (perm_mode == RMO_PERM_PFHT);
+    return sched_walk(m, r, &is_perm, out, cap, 0) / 3;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Alg. 2: p-FHT-FSCL on node RM(r,m) with L paths.                          */
+/* In:  alpha[l] (n = 2^m LLRs), pm_in[l].                                    */
+/* Out: x[l] (n bits as bytes), pm_out[l], anc[l] = input path from which    */
+/*      output path l descends (the index written l_org in the listing when  */
+/*      it refers to the surviving ancestor).                                 */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const rmo_decoder *dec;
+    int d;         /* which of the M parallel decoders (Alg. 5) */
+    int is_perm;   /* isPermutation */
+    int perm_node; /* index of the next permutation-domain node */
+} ctx_t;
+
+static float **alloc_fvecs(int L, int n)
+{
+    float **v = malloc((size_t)L * sizeof *v);
+    for (int l = 0; l < L; l++)
+        v[l] = malloc((size_t)n * sizeof **v);
+    return v;
+}
+
+static uint8_t **alloc_bvecs(int L, int n)
+{
+    uint8_t **v = malloc((size_t)L * sizeof *v);
+    for (int l = 0; l < L; l++)
+        v[l] = malloc((size_t)n);
+    return v;
+}
+
+static void free_vecs(void **v, int L)
+{
+    for (int l = 0; l < L; l++)
+        free(v[l]);
+    free(v);
+}
+
+static void node_decode(ctx_t *c, int r, int m, float *const *alpha, const float *pm_in, uint8_t **x,
+                        float *pm_out, int *anc)
+{
+    const int L = c->dec->L;
+    const int n = 1 << m;
+    const int h = n / 2;
+
+    if (1 < r && r < m - 1) {
+        float *const *wa = alpha; /* the LLR vectors the children are built from */
+        const float *wpm = pm_in;
+        float **pa = NULL;
+        float ppm[MAXL];
+        int is_per = 0;
+        int sel[2 * MAXL];
+        int origin[MAXL];
+        const amap *cands = NULL;
+
+        if (c->is_perm) {
+            /* Permutation domain: 2L candidates, candidate cc permutes the LLRs
+             * of path cc mod L; LM = sum |f(permuted)|; keep the L largest. */
+            is_per = 1;
+            cands = &c->dec->cand[((size_t)c->d * c->dec->n_perm_nodes + c->perm_node) * 2 * L];
+            c->perm_node++;
+            float lm[2 * MAXL];
+            float *t = malloc((size_t)n * sizeof *t);
+            float *fv = malloc((size_t)h * sizeof *fv);
+            for (int cc = 0; cc < 2 * L; cc++) {
+                const int src = cc % L;
+                for (int i = 0; i < n; i++)
+                    t[i] = alpha[src][amap_apply(&cands[cc], (uint32_t)i)];
+                for (int i = 0; i < h; i++)
+                    fv[i] = fabsf(f_minsum(t[i], t[i + h]));
+                lm[cc] = tree_sum(fv, h);
+            }
+            for (int cc = 0; cc < 2 * L; cc++)
+                sel[cc] = cc;
+            stable_sort_desc(sel, lm, 2 * L); /* largest reliability first, ties to lower cc */
+            pa = alloc_fvecs(L, n);
+            for (int l = 0; l < L; l++) {
+                origin[l] = sel[l] % L;
+                for (int i = 0; i < n; i++)
+                    pa[l][i] = alpha[origin[l]][amap_apply(&cands[sel[l]], (uint32_t)i)];
+                ppm[l] = pm_in[origin[l]];
+            }
+            wa = pa;
+            wpm = ppm;
+            free(t);
+            free(fv);
+        }
+
+        /* left child RM(r-1, m-1) on f */
+        float **aL = alloc_fvecs(L, h);
+        uint8_t **xL = alloc_bvecs(L, h);
+        float pmL[MAXL];
+        int ancL[MAXL];
+        for (int l = 0; l < L; l++)
+            for (int i = 0; i < h; i++)
+                aL[l][i] = f_minsum(wa[l][i], wa[l][i + h]);
+        node_decode(c, r - 1, m - 1, aL, wpm, xL, pmL, ancL);
+
+        /* right child RM(r, m-1) on g, reading the surviving ancestor's LLRs */
+        float **aR = alloc_fvecs(L, h);
+        uint8_t **xR = alloc_bvecs(L, h);
+        float pmR[MAXL];
+        int ancR[MAXL];
+        for (int l = 0; l < L; l++)
+            for (int i = 0; i < h; i++)
+                aR[l][i] = g_func(wa[ancL[l]][i], wa[ancL[l]][i + h], xL[l][i]);
+        node_decode(c, r, m - 1, aR, pmL, xR, pmR, ancR);
+
+        /* combine (x_gamma xor x_lambda, x_gamma) and undo the node's permutation */
+        uint8_t *xv = malloc((size_t)n);
+        for (int l = 0; l < L; l++) {
+            const int k = ancR[l];
+            for (int i = 0; i < h; i++) {
+                xv[i] = (uint8_t)(xR[l][i] ^ xL[k][i]);
+                xv[i + h] = xR[l][i];
+            }
+            const int a = ancL[k];
+            if (is_per) {
+                for (int i = 0; i < n; i++)
+                    x[l][amap_apply(&cands[sel[a]], (uint32_t)i)] = xv[i];
+                anc[l] = origin[a];
+            } else {
+                memcpy(x[l], xv, (size_t)n);
+                anc[l] = a;
+            }
+            pm_out[l] = pmR[l];
+        }
+        free(xv);
+        free_vecs((void **)aL, L);
+        free_vecs((void **)xL, L);
+        free_vecs((void **)aR, L);
+        free_vecs((void **)xR, L);
+        if (pa)
+            free_vecs((void **)pa, L);
+    } else if (r == 1) {
+        c->is_perm = 0;
+        fhtl_node(m, L, alpha, pm_in, x, pm_out, anc);
+    } else if (r == m - 1) {
+        spcl_node(m, L, alpha, pm_in, x, pm_out, anc);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Alg. 5: M decoders on the same y; keep the codeword of the smallest final */
+/* metric (a later decoder replaces it only if strictly smaller).  Each      */
+/* decoder starts its L paths from y permuted by its initial maps, and the   */
+/* surviving codeword is mapped back through the inverse at the root.        */
+/* If no metric is ever below +inf (non-finite input) x is all zero.          */
+/* ------------------------------------------------------------------------ */
+int rmo_decode(const rmo_decoder *d, const float *y, uint8_t *xhat, float *pm)
+{
+    const int m = d->m, L = d->L, n = 1 << m;
+    float best = INFINITY;
+    memset(xhat, 0, (size_t)n);
+    float **a = alloc_fvecs(L, n);
+    uint8_t **x = alloc_bvecs(L, n);
+    uint8_t *xo = malloc((size_t)n);
+    float pm0[MAXL], pmo[MAXL];
+    int anc[MAXL];
+    for (int p = 0; p < d->P; p++) {
+        for (int l = 0; l < L; l++) {
+            const amap *ai = &d->init[(size_t)p * L + l];
+            for (int i = 0; i < n; i++)
+                a[l][i] = y[amap_apply(ai, (uint32_t)i)];
+            pm0[l] = 0.0f;
+        }
+        ctx_t c = {d, p, d->mode == RMO_PERM_PFHT, 0};
+        node_decode(&c, d->r, m, a, pm0, x, pmo, anc);
+        int ls = 0;
+        for (int l = 1; l < L; l++)
+            if (pmo[l] < pmo[ls])
+                ls = l;
+        if (pmo[ls] < best) {
+            best = pmo[ls];
+            const amap *ai = &d->init[(size_t)p * L + anc[ls]];
+            for (int i = 0; i < n; i++)
+                xo[amap_apply(ai, (uint32_t)i)] = x[ls][i];
+            memcpy(xhat, xo, (size_t)n);
+        }
+    }
+    *pm = best;
+    free_vecs((void **)a, L);
+    free_vecs((void **)x, L);
+    free(xo);
+    return 0;
+}
+
+typedef struct {
+    const rmo_decoder *d;
+    const float *llr;
+    int64_t f0, f1;
+    uint8_t *out_bits;
+    float *out_pm;
+} job_t;
+
+static void *batch_worker(void *arg)
+{
+    job_t *j = arg;
+    const int n = 1 << j->d->m;
+    uint8_t *x = malloc((size_t)n);
+    for (int64_t f = j->f0; f < j->f1; f++) {
+        float pm;
+        rmo_decode(j->d, j->llr + f * n, x, &pm);
+        uint8_t *ob = j->out_bits + f * (n / 8);
+        memset(ob, 0, (size_t)n / 8);
+        for (int i = 0; i < n; i++)
+            ob[i >> 3] |= (uint8_t)(x[i] << (i & 7));
+        if (j->out_pm)
+            j->out_pm[f] = pm;
+    }
+    free(x);
+    return NULL;
+}
+
+int rmo_decode_batch(const rmo_decoder *d, const float *llr, int64_t n_frames, uint8_t *out_bits, float *out_pm,
+                     int n_threads)
+{
+    if (!d || n_frames < 0 || (1 << d->m) < 8)
+        return -1;
+    if (n_threads < 1)
+        n_threads = 1;
+    if (n_threads > 256)
+        n_threads = 256;
+    pthread_t th[256];
+    job_t jobs[256];
+    const int64_t per = (n_frames + n_threads - 1) / n_threads;
+    int started = 0;
+    for (int t = 0; t < n_threads; t++) {
+        int64_t f0 = t * per, f1 = f0 + per;
+        if (f0 >= n_frames)
+            break;
+        if (f1 > n_frames)
+            f1 = n_frames;
+        jobs[t] = (job_t){d, llr, f0, f1, out_bits, out_pm};
+        pthread_create(&th[t], NULL, batch_worker, &jobs[t]);
+        started++;
+    }
+    for (int t = 0; t < started; t++)
+        pthread_join(th[t], NULL);
+    return 0;
+}

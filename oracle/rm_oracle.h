@@ -1,0 +1,55 @@
+/*
+ * rm_oracle.h -- TEST INFRASTRUCTURE, not product code.
+ *
+ * Plain, slow, single-threaded CPU oracle for permuted fast successive-
+ * cancellation list decoding of Reed-Muller codes with the fast Hadamard
+ * transform (p-FHT-FSCL-L-M), written from Doan, Hashemi and Gross,
+ * "Successive-Cancellation Decoding of Reed-Muller Codes with Fast Hadamard
+ * Transform" (arXiv 2108.12550).  Only tests/, __graft_entry__.smoke() and
+ * bench.py's cpu_baseline leg may load it.  It shares no code, header, table
+ * or generator with the HIP decoder under paper_2108_12550_amd/.
+ *
+ * Notation follows the paper: RM(r, m) has order r and length N = 2^m.
+ */
+#ifndef RM_ORACLE_H
+#define RM_ORACLE_H
+#include <stdint.h>
+
+#define RMO_PERM_NONE 0   /* FHT-FSCL: identity, no permutation domain */
+#define RMO_PERM_PFHT 1   /* p-FHT-FSCL: Alg. 2 permutation domain      */
+
+typedef struct rmo_decoder rmo_decoder;
+
+/* Node kinds reported by rmo_schedule (preorder). */
+#define RMO_NODE_INTERNAL 0
+#define RMO_NODE_PERM     1   /* internal node decoded in the permutation domain */
+#define RMO_NODE_FHTL     2
+#define RMO_NODE_SPCL     3
+
+rmo_decoder *rmo_create(int m, int r, int P, int L, int perm_mode, uint64_t seed);
+void rmo_destroy(rmo_decoder *d);
+
+/* Decode one received LLR vector y (N floats).  xhat: N bytes (0/1). */
+int rmo_decode(const rmo_decoder *d, const float *y, uint8_t *xhat, float *pm);
+
+/* Decode n_frames frames; out_bits holds N/8 bytes per frame, bit i of the
+ * codeword at byte i>>3, bit i&7.  Frames are sharded over n_threads threads,
+ * each running the single-threaded decoder above unchanged. */
+int rmo_decode_batch(const rmo_decoder *d, const float *llr, int64_t n_frames,
+                     uint8_t *out_bits, float *out_pm, int n_threads);
+
+/* Pieces exposed for the pin tests. */
+int rmo_info_set(int m, int r, uint8_t *is_info);                 /* N flags */
+int rmo_encode(int m, const uint8_t *u, uint8_t *x);               /* x = u G^{(x)m} */
+int rmo_fht(int s, int L, const float *alpha, float pm_in,
+            uint8_t *cw, float *pm, int *idx);                     /* Alg. 4 */
+int rmo_spcl(int s, int L, const float *alpha, const float *pm_in,
+             uint8_t *x, float *pm, int *anc);                     /* Eqs. (2)-(6) */
+int rmo_fhtl(int s, int L, const float *alpha, const float *pm_in,
+             uint8_t *x, float *pm, int *anc);                     /* Alg. 3 */
+int rmo_schedule(int m, int r, int perm_mode, int *out, int cap);  /* (kind,r,m) triples */
+int rmo_perm_count(const rmo_decoder *d);
+int rmo_perm_export(const rmo_decoder *d, uint16_t *rows, uint16_t *b, int *mdim, int cap);
+uint64_t rmo_splitmix64_next(uint64_t *state);
+
+#endif

@@ -1,0 +1,351 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these checks re-types the oracle's formulas: each compares it with a
+printed value (tests/golden/paper_values.json, cited there), a brute-force
+search over all codewords of a small code, a closed form or an exact
+invariant of the decoder.  Runs on the CPU only.
+"""
+import itertools
+import json
+import os
+from math import comb
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+
+
+# --------------------------------------------------------------------------
+# independent helpers (plain definitions, float64)
+# --------------------------------------------------------------------------
+
+def first_order_codewords(s):
+    """All 2^(s+1) codewords of RM(1,s): x(z) = b0 + <c, z> over F2."""
+    n = 1 << s
+    z = np.arange(n)
+    out = []
+    for c in range(n):
+        lin = np.array([bin(c & zz).count("1") & 1 for zz in z], dtype=np.uint8)
+        out.append(lin)
+        out.append(lin ^ 1)
+    return np.array(out)
+
+
+def corr_metric(x, llr):
+    """Sum of |llr_i| over positions where x disagrees with the hard decision."""
+    llr = np.asarray(llr, dtype=np.float64)
+    hd = (llr < 0).astype(np.uint8)
+    return float(np.sum(np.abs(llr) * (np.asarray(x) != hd)))
+
+
+def all_codewords(m, r):
+    mon = synth.monomial_table(m, r)
+    k = mon.shape[0]
+    coefs = np.array(list(itertools.product([0, 1], repeat=k)), dtype=np.int64)
+    return ((coefs @ mon.astype(np.int64)) & 1).astype(np.uint8)
+
+
+def is_codeword(x, m, r):
+    u = oracle.encode(m, x)  # G^{(x)m} is its own inverse over F2
+    info = oracle.info_set(m, r)
+    return not np.any(u[info == 0])
+
+
+def wilson(k, n, z):
+    p = k / n
+    den = 1 + z * z / n
+    c = (p + z * z / (2 * n)) / den
+    h = z * np.sqrt(p * (1 - p) / n + z * z / (4 * n * n)) / den
+    return c - h, c + h
+
+
+# --------------------------------------------------------------------------
+# O0: code tables
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name,k", [(k, v) for k, v in GOLDEN["code_dimensions"].items() if not k.startswith("_")])
+def test_code_dimension_printed(name, k):
+    r, m = map(int, name[3:-1].split(","))
+    assert int(oracle.info_set(m, r).sum()) == k
+    assert sum(comb(m, i) for i in range(r + 1)) == k
+
+
+def test_rm13_info_set():
+    assert list(np.nonzero(oracle.info_set(3, 1))[0]) == GOLDEN["rm13_info_set"]["value"]
+
+
+@pytest.mark.parametrize("m,r", [(3, 1), (4, 1), (4, 2), (5, 2), (5, 1)])
+def test_code_is_rm_minimum_distance(m, r):
+    """The oracle's u G^{(x)m} code equals the polynomial code and has d = 2^(m-r)."""
+    n = 1 << m
+    idx = np.nonzero(oracle.info_set(m, r))[0]
+    basis = []
+    for i in idx:
+        u = np.zeros(n, dtype=np.uint8)
+        u[i] = 1
+        basis.append(oracle.encode(m, u))
+    basis = np.array(basis, dtype=np.int64)
+    coefs = np.array(list(itertools.product([0, 1], repeat=len(idx))), dtype=np.int64)
+    words = (coefs @ basis) & 1
+    assert {w.tobytes() for w in words.astype(np.uint8)} == {w.tobytes() for w in all_codewords(m, r)}
+    wts = words.sum(axis=1)
+    assert wts[wts > 0].min() == 2 ** (m - r)
+
+
+def test_rm35_schedule():
+    got = [list(t) for t in oracle.schedule(5, 3)]
+    assert got == GOLDEN["rm35_schedule"]["value"]
+
+
+@pytest.mark.parametrize("m,r,expect", [
+    (9, 2, [("perm", 2, 9), ("fhtl", 1, 8)]),
+    (8, 3, [("perm", 3, 8), ("perm", 2, 7), ("fhtl", 1, 6)]),
+])
+def test_schedule_perm_domain(m, r, expect):
+    s = oracle.schedule(m, r)
+    assert s[:len(expect)] == expect
+    assert all(k != "perm" for k, _, _ in s[len(expect):])
+    n_spc = sum(k == "spcl" for k, _, _ in s)
+    n_fht = sum(k == "fhtl" for k, _, _ in s)
+    if (m, r) == (9, 2):
+        assert (n_fht, n_spc) == (6, 1)
+    if (m, r) == (8, 3):
+        assert (n_fht, n_spc) == (10, 5)
+
+
+# --------------------------------------------------------------------------
+# O1: permutations
+# --------------------------------------------------------------------------
+
+def test_splitmix64_published_constants():
+    # SplitMix64 from seed 0 (first outputs of the published generator).
+    assert oracle.splitmix64(0, 3) == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+@pytest.mark.parametrize("m,r,L", [(5, 2, 2), (6, 3, 4), (7, 2, 1)])
+def test_perms_are_automorphisms(m, r, L):
+    dec = oracle.OracleDecoder(m, r, 2, L, seed=11)
+    words = all_codewords(min(m, 5), r) if m <= 5 else None
+    for rows, b in dec.perms():
+        md = len(rows)
+        n = 1 << md
+        p = np.array([(sum(((bin(int(rows[j]) & i).count("1") & 1) << j) for j in range(md)) ^ b)
+                      for i in range(n)])
+        assert sorted(p) == list(range(n))  # bijection
+        # an affine map keeps every codeword of RM(r', md) a codeword
+        rr = min(r, md - 1)
+        rng = np.random.default_rng(md)
+        mon = synth.monomial_table(md, rr)
+        for _ in range(8):
+            x = (rng.integers(0, 2, mon.shape[0]) @ mon) & 1
+            assert is_codeword(x[p].astype(np.uint8), md, rr)
+    del words
+
+
+# --------------------------------------------------------------------------
+# O4: FHT decoding (Alg. 4) against brute force over RM(1,s)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("s", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("L", [1, 2, 4, 8])
+def test_fht_candidates_are_best_codewords(s, L):
+    rng = np.random.default_rng(100 * s + L)
+    words = first_order_codewords(s)
+    for trial in range(20):
+        alpha = rng.normal(0.8, 1.3, 1 << s).astype(np.float32)
+        pm_in = float(rng.uniform(0, 3))
+        cw, pm, _ = oracle.fht(s, L, alpha, pm_in)
+        bf = best_metrics(words, alpha)
+        k = min(L, 1 << s)
+        tol = 1e-5 * (np.abs(alpha).sum() + pm_in) + 1e-6
+        for j in range(k):
+            # candidate is a codeword of RM(1,s) and carries its own metric (Eq. (9))
+            assert any(np.array_equal(cw[j], w) for w in words)
+            assert abs(pm[j] - (pm_in + corr_metric(cw[j], alpha))) < tol
+        # and the k candidates are the k best codewords
+        np.testing.assert_allclose(np.sort(pm) - pm_in, bf[:k], atol=tol)
+        assert np.all(np.diff(pm) >= 0)
+
+
+def test_fht_ties_go_to_lower_index():
+    # all-zero input: every |F| is 0; the candidates are indices 0,1,2,... in order
+    cw, pm, idx = oracle.fht(3, 4, np.zeros(8, np.float32), 0.0)
+    assert list(idx) == [0, 1, 2, 3]
+
+
+# --------------------------------------------------------------------------
+# O5: SPC rules against exhaustive search over even-weight words
+# --------------------------------------------------------------------------
+
+def even_words(n):
+    v = np.arange(1 << n, dtype=np.int64)
+    bits = ((v[:, None] >> np.arange(n)) & 1).astype(np.uint8)
+    return bits[bits.sum(axis=1) % 2 == 0]
+
+
+def best_metrics(words, llr):
+    """Correlation metrics of all words against llr, ascending (float64)."""
+    llr = np.asarray(llr, dtype=np.float64)
+    hd = (llr < 0).astype(np.uint8)
+    return np.sort(((words != hd) * np.abs(llr)).sum(axis=1))
+
+
+@pytest.mark.parametrize("s", [2, 3, 4])
+def test_spc_wagner_is_ml(s):
+    rng = np.random.default_rng(s)
+    words = even_words(1 << s)
+    for _ in range(30):
+        alpha = rng.normal(0.5, 1.5, 1 << s).astype(np.float32)
+        x, pm, anc = oracle.spcl(s, 1, alpha[None], np.zeros(1, np.float32))
+        best = best_metrics(words, alpha)[0]
+        assert x[0].sum() % 2 == 0
+        assert abs(pm[0] - best) < 1e-5 * np.abs(alpha).sum() + 1e-6
+        assert abs(corr_metric(x[0], alpha) - pm[0]) < 1e-5 * np.abs(alpha).sum() + 1e-6
+
+
+@pytest.mark.parametrize("s,L", [(3, 2), (3, 4), (3, 8), (4, 4), (4, 8)])
+def test_spc_list_single_path_gives_best_words(s, L):
+    """One live path (the others carry a huge metric): the L outputs are the L
+    best even-weight words, each with its own correlation metric."""
+    rng = np.random.default_rng(10 * s + L)
+    n = 1 << s
+    words = even_words(n)
+    for _ in range(20):
+        alpha = np.zeros((L, n), np.float32)
+        alpha[0] = rng.normal(0.5, 1.5, n)
+        pm_in = np.full(L, 1e30, np.float32)
+        pm_in[0] = 0.0
+        x, pm, anc = oracle.spcl(s, L, alpha, pm_in)
+        tol = 1e-5 * np.abs(alpha[0]).sum() + 1e-6
+        bf = best_metrics(words, alpha[0])
+        live = min(L, n // 2)  # even words reachable within tau flips is at least this
+        for q in range(live):
+            assert anc[q] == 0
+            assert x[q].sum() % 2 == 0
+            assert abs(pm[q] - corr_metric(x[q], alpha[0])) < tol
+        np.testing.assert_allclose(pm[:min(L, len(bf))][:live], bf[:live], atol=tol)
+
+
+# --------------------------------------------------------------------------
+# Whole decoder (Alg. 5 over Alg. 2): invariants
+# --------------------------------------------------------------------------
+
+CODES = [(5, 2), (6, 3), (6, 2), (7, 3), (7, 2)]
+
+
+@pytest.mark.parametrize("m,r", CODES)
+@pytest.mark.parametrize("L,P", [(1, 1), (1, 3), (2, 2), (4, 2), (8, 1)])
+def test_decoder_invariants(m, r, L, P):
+    n = 1 << m
+    dec = oracle.OracleDecoder(m, r, P, L, seed=7 + L + P)
+    x0, llr = synth.frames(m, r, 40, 1.0, seed=m * 10 + r)
+    for f in range(llr.shape[0]):
+        x, pm = dec.decode(llr[f])
+        # the output is a codeword
+        assert is_codeword(x, m, r)
+        # its final metric is the correlation metric of that codeword (exact
+        # for min-sum f and exact g; here up to binary32 rounding)
+        ref = corr_metric(x, llr[f])
+        assert abs(pm - ref) <= 1e-5 * max(1.0, ref) + 1e-4, (f, pm, ref)
+
+
+@pytest.mark.parametrize("m,r,L,P", [(5, 2, 4, 2), (7, 2, 4, 3), (6, 3, 8, 1), (8, 3, 2, 2)])
+def test_noiseless(m, r, L, P):
+    dec = oracle.OracleDecoder(m, r, P, L, seed=3)
+    rng = np.random.default_rng(1)
+    mon = synth.monomial_table(m, r)
+    for _ in range(5):
+        x = ((rng.integers(0, 2, mon.shape[0]) @ mon) & 1).astype(np.uint8)
+        y = (4.0 * (1 - 2.0 * x)).astype(np.float32)
+        xh, pm = dec.decode(y)
+        assert np.array_equal(xh, x) and pm == 0.0
+
+
+@pytest.mark.parametrize("m,r,L,P", [(5, 2, 4, 2), (7, 2, 4, 2), (6, 3, 8, 1), (7, 3, 2, 3)])
+def test_codeword_sign_flip_equivariance(m, r, L, P):
+    """decode(y * (1-2c)) = decode(y) xor c with the identical metric."""
+    dec = oracle.OracleDecoder(m, r, P, L, seed=5)
+    rng = np.random.default_rng(2)
+    mon = synth.monomial_table(m, r)
+    _, llr = synth.frames(m, r, 10, 1.5, seed=99)
+    for f in range(llr.shape[0]):
+        c = ((rng.integers(0, 2, mon.shape[0]) @ mon) & 1).astype(np.uint8)
+        xa, pa = dec.decode(llr[f])
+        xb, pb = dec.decode((llr[f] * (1 - 2.0 * c)).astype(np.float32))
+        assert np.array_equal(xb, xa ^ c)
+        assert pa == pb
+
+
+@pytest.mark.parametrize("m", [3, 4, 5, 6])
+@pytest.mark.parametrize("L", [1, 4])
+def test_first_order_root_is_ml(m, L):
+    words = first_order_codewords(m)
+    dec = oracle.OracleDecoder(m, 1, 2, L, seed=1)
+    _, llr = synth.frames(m, 1, 20, 0.0, seed=m)
+    for f in range(llr.shape[0]):
+        x, pm = dec.decode(llr[f])
+        best = best_metrics(words, llr[f])[0]
+        assert abs(corr_metric(x, llr[f]) - best) < 1e-5 * np.abs(llr[f]).sum()
+
+
+@pytest.mark.parametrize("m", [3, 4])
+def test_spc_root_l1_is_wagner(m):
+    words = even_words(1 << m)
+    dec = oracle.OracleDecoder(m, m - 1, 1, 1, seed=1)
+    _, llr = synth.frames(m, m - 1, 20, 1.0, seed=m)
+    for f in range(llr.shape[0]):
+        x, pm = dec.decode(llr[f])
+        best = best_metrics(words, llr[f])[0]
+        assert abs(pm - best) < 1e-5 * np.abs(llr[f]).sum() + 1e-6
+
+
+def test_exhaustive_ml_rm25():
+    """RM(2,5), K = 16: the decoder never beats ML and agrees with it at high SNR."""
+    words = all_codewords(5, 2).astype(np.float64)
+    eta = 1.0 - 2.0 * words
+    dec = oracle.OracleDecoder(5, 2, 4, 4, seed=21)
+    _, llr = synth.frames(5, 2, 400, 6.0, seed=5)
+    agree = 0
+    for f in range(llr.shape[0]):
+        x, pm = dec.decode(llr[f])
+        y = llr[f].astype(np.float64)
+        ml = 0.5 * (np.abs(y).sum() - (eta @ y).max())
+        assert pm >= ml - 1e-4 * max(1.0, ml)
+        agree += abs(pm - ml) <= 1e-4 * max(1.0, ml)
+    assert agree / llr.shape[0] >= 0.99
+
+
+def test_none_mode_requires_single_path():
+    with pytest.raises(ValueError):
+        oracle.OracleDecoder(7, 2, 1, 4, perm_mode=oracle.PERM_NONE)
+
+
+# --------------------------------------------------------------------------
+# Statistical pins: FER against the printed curves (Fig. 5(a)), which also
+# pins the Eb/N0 convention and the permutation-domain reading.
+# --------------------------------------------------------------------------
+
+def _fer(m, r, P, L, mode, ebn0, n, seed):
+    dec = oracle.OracleDecoder(m, r, P, L, seed=seed, perm_mode=mode)
+    x, llr = synth.frames(m, r, n, ebn0, seed=seed + 1000)
+    bits, _ = dec.decode_batch(llr, n_threads=os.cpu_count() or 1)
+    xh = synth.unpack_bits(bits, 1 << m)
+    return int(np.any(xh != x, axis=1).sum())
+
+
+@pytest.mark.parametrize("name,mode,L,ebn0,n", [
+    ("FHT-FSCL-1", oracle.PERM_NONE, 1, "3.0", 4000),
+    ("FHT-FSCL-1", oracle.PERM_NONE, 1, "2.0", 2000),
+    ("p-FHT-FSC-1", oracle.PERM_PFHT, 1, "3.0", 12000),
+    ("p-FHT-FSC-2", oracle.PERM_PFHT, 2, "3.0", 12000),
+    ("p-FHT-FSCL-4", oracle.PERM_PFHT, 4, "2.5", 3000),
+])
+def test_fer_matches_fig5(name, mode, L, ebn0, n):
+    pub = GOLDEN["fer_rm29"][name][ebn0]
+    k = _fer(9, 2, 1, L, mode, float(ebn0), n, seed=31)
+    lo, hi = wilson(k, n, 3.29)  # 99.9% interval
+    assert lo <= pub <= hi, (name, ebn0, k / n, pub)
