@@ -1,0 +1,126 @@
+/*
+ * rmdec.h -- C ABI of the MI355X (gfx950) batched decoder for Reed-Muller
+ * codes: permuted fast successive-cancellation list decoding with the fast
+ * Hadamard transform, run as M parallel decoders per frame (p-FHT-FSCL-L-M).
+ *
+ * The operation follows Doan, Hashemi and Gross, "Successive-Cancellation
+ * Decoding of Reed-Muller Codes with Fast Hadamard Transform" (arXiv
+ * 2108.12550): Alg. 5 (M decoders, minimum final metric) over Alg. 2
+ * (permutation-domain path extension until the first order-1 node), Alg. 3
+ * and Alg. 4 (FHT list decoding of RM(1,s) nodes with the metric of
+ * Eq. (10)) and the SPC list rules of Eqs. (2)-(6).
+ *
+ * Naming: the paper writes RM(r, m) with order r and length N = 2^m; every
+ * function here takes m and r as separately named arguments.  "P" below is
+ * the number of parallel decoders (the paper's M).
+ *
+ * Memory: every array argument of rm_decode_batch is DEVICE memory owned by
+ * the caller.  The library owns its permutation tables (device memory,
+ * allocated at create, freed at destroy) and nothing else; it keeps no
+ * reference to caller buffers after the work it queued has completed.
+ *
+ * Errors: functions returning int give RM_OK (0) or a negative code; a
+ * thread-local message is available from rm_last_error().
+ */
+#ifndef RMDEC_H
+#define RMDEC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RM_OK 0
+#define RM_E_INVAL (-1)       /* argument outside the documented domain          */
+#define RM_E_NOMEM (-2)       /* host or device allocation failed                */
+#define RM_E_HIP (-3)         /* a HIP runtime call failed (message has details) */
+#define RM_E_UNSUPPORTED (-4) /* no kernel built for this (m, r, L, mode)        */
+#define RM_E_PTR (-5)         /* a host pointer was passed where device memory is required */
+
+/* Permutation mode. */
+#define RM_PERM_NONE 0 /* FHT-FSCL: identity, no permutation domain (needs L = 1) */
+#define RM_PERM_PFHT 1 /* p-FHT-FSCL: random affine permutations (Alg. 2)         */
+
+typedef struct rm_decoder rm_decoder;
+
+typedef struct rm_config {
+    int m;               /* 3 <= m <= 10, N = 2^m                                  */
+    int r;               /* 1 <= r <= m-1                                          */
+    int P;               /* parallel decoders per frame (paper's M), 1..1024      */
+    int L;               /* list size per decoder: 1, 2, 4 or 8                   */
+    uint64_t seed;       /* seed of the permutation draw (SplitMix64)             */
+    int perm_mode;       /* RM_PERM_PFHT or RM_PERM_NONE                          */
+    int waves_per_block; /* 0 = library choice; else 1..4 wavefronts per block   */
+} rm_config;
+
+typedef struct rm_info {
+    int m, r, P, L, N, K;
+    int perm_mode;
+    int n_perm_nodes;       /* internal nodes decoded in the permutation domain  */
+    int maps_per_decoder;   /* affine maps stored per decoder                    */
+    int waves_per_block;
+    size_t lds_bytes_per_wave;
+    size_t table_bytes;     /* device bytes of the permutation tables            */
+} rm_info;
+
+/*
+ * Create a decoder for RM(r, m) with P parallel decoders of list size L in
+ * the p-FHT-FSCL mode.  The random permutations (Alg. 2's initial maps and
+ * the 2L candidate maps of every permutation-domain node) are drawn once,
+ * here, from `seed`, as uniform elements of the affine group AGL(m, 2), the
+ * full symmetry group of the code.  Draw order, per decoder d = 0..P-1: the
+ * L initial maps, then 2L candidate maps per permutation-domain node in
+ * preorder; each map draws the m rows of A (low m bits of one SplitMix64
+ * output each, redrawn as a whole until A is invertible), then b.
+ * Returns NULL on error (see rm_last_error()); needs a HIP device.
+ */
+rm_decoder *rm_decoder_create(int m, int r, int P, int L, uint64_t seed);
+
+/* As rm_decoder_create, with a permutation mode and a launch override. */
+rm_decoder *rm_decoder_create_ex(const rm_config *cfg);
+
+/*
+ * Decode n_frames received frames (Alg. 5 per frame).
+ *   llr        device, n_frames x N float32, frame-major; LLR = ln P(0)/P(1)
+ *              (positive means bit 0).  Values must be finite.
+ *   out_bits   device, n_frames x N/8 bytes: the decoded codeword x_hat,
+ *              bit i of frame f at byte f*N/8 + (i>>3), bit (i&7).
+ *   out_metric device, n_frames float32 final path metrics, or NULL.
+ * Work is queued on the decoder's stream (rm_decoder_set_stream; default the
+ * null stream) and the call returns without waiting.  n_frames = 0 is a
+ * no-op.  Results depend only on (m, r, P, L, seed, perm_mode, llr).
+ */
+int rm_decode_batch(rm_decoder *d, const float *llr, int64_t n_frames, uint8_t *out_bits, float *out_metric);
+
+/* Release the decoder after the work queued on its stream completes.  NULL-safe. */
+void rm_decoder_destroy(rm_decoder *d);
+
+/* Bind a hipStream_t (passed as void*) for later rm_decode_batch calls. */
+int rm_decoder_set_stream(rm_decoder *d, void *hip_stream);
+
+/* Report the decoder's sizes and launch shape. */
+int rm_decoder_info(const rm_decoder *d, rm_info *out);
+
+/*
+ * Host only (no device needed): run the permutation draw of
+ * rm_decoder_create_ex for (m, r, P, L, seed, perm_mode) and return every
+ * drawn map in draw order: rows[k*16 + j] = row j of A_k (bit i of the row
+ * multiplies bit i of the position index), b[k], mdim[k] = its dimension.
+ * Returns the number of maps, or a negative code if cap is too small.
+ * For cross-checking the draw against an independent implementation.
+ */
+int rm_perm_tables(int m, int r, int P, int L, uint64_t seed, int perm_mode, uint16_t *rows, uint16_t *b,
+                   int *mdim, int cap);
+
+/* 1 if a kernel is built for (m, r, L, perm_mode), else 0.  Host only. */
+int rm_supported(int m, int r, int L, int perm_mode);
+
+/* Message of the last error on this thread ("" if none). */
+const char *rm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,91 @@
+"""MI355X (gfx950) batched decoder for Reed-Muller codes.
+
+Permuted fast successive-cancellation list decoding with the fast Hadamard
+transform, P parallel decoders per frame (p-FHT-FSCL-L-M; Doan, Hashemi and
+Gross, arXiv 2108.12550, Alg. 2-5).  All decoding runs in the HIP kernels of
+librmdec.so behind the C ABI of include/rmdec.h; PyTorch provides device
+memory and streams only.
+"""
+from __future__ import annotations
+
+from math import comb
+
+from . import _lib
+from ._lib import (RM_E_HIP, RM_E_INVAL, RM_E_NOMEM, RM_E_PTR, RM_E_UNSUPPORTED, RM_OK, RM_PERM_NONE,
+                   RM_PERM_PFHT, rm_config, rm_decode_batch, rm_decoder_create, rm_decoder_create_ex,
+                   rm_decoder_destroy, rm_decoder_info, rm_decoder_set_stream, rm_last_error, rm_perm_tables,
+                   rm_supported)
+
+__all__ = ["Decoder", "perm_tables", "code_dimension", "RM_PERM_NONE", "RM_PERM_PFHT", "rm_config",
+           "rm_decode_batch", "rm_decoder_create", "rm_decoder_create_ex", "rm_decoder_destroy",
+           "rm_decoder_info", "rm_decoder_set_stream", "rm_last_error", "rm_perm_tables", "rm_supported"]
+
+
+def code_dimension(m: int, r: int) -> int:
+    return sum(comb(m, i) for i in range(r + 1))
+
+
+class RMError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"librmdec error {code}: {msg}")
+        self.code = code
+
+
+class Decoder:
+    """p-FHT-FSCL-L-M decoder of RM(r, m) with P parallel decoders of list size L."""
+
+    def __init__(self, m: int, r: int, P: int, L: int, seed: int = 0, perm_mode: int = RM_PERM_PFHT,
+                 waves_per_block: int = 0):
+        cfg = rm_config(m, r, P, L, seed, perm_mode, waves_per_block)
+        self._h = rm_decoder_create_ex(cfg)
+        if not self._h:
+            raise RMError(-1, rm_last_error())
+        self.m, self.r, self.P, self.L, self.seed, self.perm_mode = m, r, P, L, seed, perm_mode
+        self.N = 1 << m
+        self.K = code_dimension(m, r)
+
+    def close(self):
+        if getattr(self, "_h", 0):
+            rm_decoder_destroy(self._h)
+            self._h = 0
+
+    def __del__(self):
+        self.close()
+
+    def info(self) -> dict:
+        i = rm_decoder_info(self._h)
+        return {f: getattr(i, f) for f, _ in i._fields_}
+
+    def decode(self, llr, out_bits=None, out_metric=None, stream=None):
+        """Decode a (n_frames, N) float32 CUDA tensor of LLRs.
+
+        Returns (bits, metric): (n_frames, N/8) uint8 packed codewords (bit i
+        at byte i>>3, bit i&7) and (n_frames,) float32 final metrics.  The work
+        is queued on ``stream`` (default: torch's current stream).
+        """
+        import torch
+        if not (llr.is_cuda and llr.dtype == torch.float32 and llr.is_contiguous()):
+            raise ValueError("llr must be a contiguous float32 CUDA tensor")
+        llr = llr.view(-1, self.N)
+        n = llr.shape[0]
+        if out_bits is None:
+            out_bits = torch.empty((n, self.N // 8), dtype=torch.uint8, device=llr.device)
+        if out_metric is None:
+            out_metric = torch.empty((n,), dtype=torch.float32, device=llr.device)
+        s = stream if stream is not None else torch.cuda.current_stream(llr.device)
+        rc = rm_decoder_set_stream(self._h, s.cuda_stream)
+        if rc == RM_OK:
+            rc = rm_decode_batch(self._h, llr.data_ptr(), n, out_bits.data_ptr(),
+                                 out_metric.data_ptr() if out_metric is not False else None)
+        if rc != RM_OK:
+            raise RMError(rc, rm_last_error())
+        return out_bits, out_metric
+
+
+def perm_tables(m: int, r: int, P: int, L: int, seed: int, perm_mode: int = RM_PERM_PFHT):
+    """Every affine map the decoder draws, in draw order: list of (rows, b)."""
+    cap = P * (L + 2 * L * m)
+    n, rows, b, md = rm_perm_tables(m, r, P, L, seed, perm_mode, cap)
+    if n < 0:
+        raise RMError(n, rm_last_error())
+    return [(list(rows[16 * k:16 * k + md[k]]), int(b[k])) for k in range(n)]

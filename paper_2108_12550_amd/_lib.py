@@ -1,0 +1,119 @@
+"""ctypes binding of librmdec.so: the C ABI of include/rmdec.h, same names.
+
+Argument marshalling only.  The library must have been built in-tree
+(``python -m paper_2108_12550_amd.build``); there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librmdec.so")
+
+RM_OK = 0
+RM_E_INVAL = -1
+RM_E_NOMEM = -2
+RM_E_HIP = -3
+RM_E_UNSUPPORTED = -4
+RM_E_PTR = -5
+
+RM_PERM_NONE = 0
+RM_PERM_PFHT = 1
+
+EXPORTED = ("rm_decoder_create", "rm_decoder_create_ex", "rm_decode_batch", "rm_decoder_destroy",
+            "rm_decoder_set_stream", "rm_decoder_info", "rm_perm_tables", "rm_supported", "rm_last_error")
+
+
+class rm_config(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int), ("r", ctypes.c_int), ("P", ctypes.c_int), ("L", ctypes.c_int),
+                ("seed", ctypes.c_uint64), ("perm_mode", ctypes.c_int), ("waves_per_block", ctypes.c_int)]
+
+
+class rm_info(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int), ("r", ctypes.c_int), ("P", ctypes.c_int), ("L", ctypes.c_int),
+                ("N", ctypes.c_int), ("K", ctypes.c_int), ("perm_mode", ctypes.c_int),
+                ("n_perm_nodes", ctypes.c_int), ("maps_per_decoder", ctypes.c_int),
+                ("waves_per_block", ctypes.c_int), ("lds_bytes_per_wave", ctypes.c_size_t),
+                ("table_bytes", ctypes.c_size_t)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load librmdec.so; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2108_12550_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    L.rm_decoder_create.restype = vp
+    L.rm_decoder_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64]
+    L.rm_decoder_create_ex.restype = vp
+    L.rm_decoder_create_ex.argtypes = [P(rm_config)]
+    L.rm_decode_batch.restype = ctypes.c_int
+    L.rm_decode_batch.argtypes = [vp, vp, ctypes.c_int64, vp, vp]
+    L.rm_decoder_destroy.restype = None
+    L.rm_decoder_destroy.argtypes = [vp]
+    L.rm_decoder_set_stream.restype = ctypes.c_int
+    L.rm_decoder_set_stream.argtypes = [vp, vp]
+    L.rm_decoder_info.restype = ctypes.c_int
+    L.rm_decoder_info.argtypes = [vp, P(rm_info)]
+    L.rm_perm_tables.restype = ctypes.c_int
+    L.rm_perm_tables.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                 ctypes.c_int, P(ctypes.c_uint16), P(ctypes.c_uint16), P(ctypes.c_int),
+                                 ctypes.c_int]
+    L.rm_supported.restype = ctypes.c_int
+    L.rm_supported.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.rm_last_error.restype = ctypes.c_char_p
+    L.rm_last_error.argtypes = []
+    _lib = L
+    return L
+
+
+def rm_last_error() -> str:
+    return load().rm_last_error().decode()
+
+
+def rm_decoder_create(m: int, r: int, P: int, L: int, seed: int) -> int:
+    return load().rm_decoder_create(m, r, P, L, ctypes.c_uint64(seed)) or 0
+
+
+def rm_decoder_create_ex(cfg: rm_config) -> int:
+    return load().rm_decoder_create_ex(ctypes.byref(cfg)) or 0
+
+
+def rm_decode_batch(dec: int, llr_ptr: int, n_frames: int, out_bits_ptr: int, out_metric_ptr: int | None) -> int:
+    return load().rm_decode_batch(dec, llr_ptr, n_frames, out_bits_ptr, out_metric_ptr or None)
+
+
+def rm_decoder_destroy(dec: int) -> None:
+    load().rm_decoder_destroy(dec)
+
+
+def rm_decoder_set_stream(dec: int, stream_handle: int) -> int:
+    return load().rm_decoder_set_stream(dec, stream_handle or None)
+
+
+def rm_decoder_info(dec: int) -> rm_info:
+    out = rm_info()
+    rc = load().rm_decoder_info(dec, ctypes.byref(out))
+    if rc != RM_OK:
+        raise RuntimeError(rm_last_error())
+    return out
+
+
+def rm_perm_tables(m: int, r: int, P: int, L: int, seed: int, perm_mode: int, cap: int):
+    rows = (ctypes.c_uint16 * (16 * cap))()
+    b = (ctypes.c_uint16 * cap)()
+    md = (ctypes.c_int * cap)()
+    n = load().rm_perm_tables(m, r, P, L, ctypes.c_uint64(seed), perm_mode, rows, b, md, cap)
+    return n, rows, b, md
+
+
+def rm_supported(m: int, r: int, L: int, perm_mode: int) -> bool:
+    return bool(load().rm_supported(m, r, L, perm_mode))

@@ -1,0 +1,426 @@
+// rmdec_host.hip -- the C ABI declared in include/rmdec.h: argument checks,
+// the permutation draw, the device tables and the kernel launch.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "rmdec.h"
+#include "rmdec_kernels.hpp"
+
+using namespace rmdec;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): Weyl increment, then mix.
+struct SplitMix64 {
+    uint64_t s;
+    uint64_t next()
+    {
+        s += 0x9E3779B97F4A7C15ull;
+        uint64_t z = s;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+};
+
+// Affine map p(i) = A z(i) + b over F2^m; row j of A gives output bit j.
+struct Affine {
+    int m = 0;
+    uint32_t row[16] = {};
+    uint32_t b = 0;
+    uint32_t apply(uint32_t i) const
+    {
+        uint32_t z = 0;
+        for (int j = 0; j < m; j++)
+            z |= (uint32_t)(__builtin_popcount(row[j] & i) & 1) << j;
+        return z ^ b;
+    }
+};
+
+bool invertible(const uint32_t *rows, int m)
+{
+    uint32_t t[16];
+    for (int k = 0; k < m; k++)
+        t[k] = rows[k];
+    int rank = 0;
+    for (int col = 0; col < m && rank < m; col++) {
+        int piv = -1;
+        for (int k = rank; k < m; k++)
+            if ((t[k] >> col) & 1u) {
+                piv = k;
+                break;
+            }
+        if (piv < 0)
+            continue;
+        uint32_t tmp = t[piv];
+        t[piv] = t[rank];
+        t[rank] = tmp;
+        for (int k = 0; k < m; k++)
+            if (k != rank && ((t[k] >> col) & 1u))
+                t[k] ^= t[rank];
+        rank++;
+    }
+    return rank == m;
+}
+
+Affine draw_affine(int m, SplitMix64 &rng)
+{
+    Affine a;
+    a.m = m;
+    const uint32_t mask = (1u << m) - 1u;
+    do {
+        for (int k = 0; k < m; k++)
+            a.row[k] = (uint32_t)(rng.next() & mask);
+    } while (!invertible(a.row, m));
+    a.b = (uint32_t)(rng.next() & mask);
+    return a;
+}
+
+Affine identity(int m)
+{
+    Affine a;
+    a.m = m;
+    for (int k = 0; k < m; k++)
+        a.row[k] = 1u << k;
+    return a;
+}
+
+int spine_perm_nodes(int m, int r) { return perm_spine(m, r); }
+
+struct Draw {
+    std::vector<Affine> init; // [P][L]
+    std::vector<Affine> cand; // [P][nperm][2L]
+    int nperm = 0;
+};
+
+Draw draw_all(int m, int r, int P, int L, uint64_t seed, int pfht)
+{
+    Draw d;
+    d.nperm = pfht ? spine_perm_nodes(m, r) : 0;
+    d.init.resize((size_t)P * L);
+    d.cand.resize((size_t)P * d.nperm * 2 * L);
+    SplitMix64 rng{seed};
+    for (int p = 0; p < P; p++) {
+        for (int l = 0; l < L; l++)
+            d.init[(size_t)p * L + l] = pfht ? draw_affine(m, rng) : identity(m);
+        for (int v = 0; v < d.nperm; v++)
+            for (int c = 0; c < 2 * L; c++)
+                d.cand[((size_t)p * d.nperm + v) * 2 * L + c] = draw_affine(m - v, rng);
+    }
+    return d;
+}
+
+// A map as the kernel stores it: images of the unit vectors (columns) and b,
+// obtained from the full permutation table q[i].
+void store_table(const std::vector<uint32_t> &q, int m, uint32_t *out)
+{
+    for (int k = 0; k < kMapWords; k++)
+        out[k] = 0;
+    for (int k = 0; k < m; k++)
+        out[k] = q[1u << k] ^ q[0];
+    out[kMapB] = q[0];
+    out[13] = (uint32_t)m;
+}
+
+std::vector<uint32_t> table_of(const Affine &a)
+{
+    std::vector<uint32_t> q((size_t)1 << a.m);
+    for (uint32_t i = 0; i < q.size(); i++)
+        q[i] = a.apply(i);
+    return q;
+}
+
+std::vector<uint32_t> inverse_of(const std::vector<uint32_t> &q)
+{
+    std::vector<uint32_t> r(q.size());
+    for (uint32_t i = 0; i < q.size(); i++)
+        r[q[i]] = i;
+    return r;
+}
+
+const KernelEntry *find_kernel(int m, int r, int L)
+{
+    const KernelTable tabs[] = {kernels_codes_a(), kernels_codes_b(), kernels_codes_c(), kernels_codes_d()};
+    for (const KernelTable &t : tabs)
+        for (int i = 0; i < t.count; i++)
+            if (t.entries[i].m == m && t.entries[i].r == r && t.entries[i].L == L)
+                return &t.entries[i];
+    return nullptr;
+}
+
+int check_params(int m, int r, int P, int L, int perm_mode)
+{
+    if (m < 3 || m > 10)
+        return fail(RM_E_INVAL, "m must be in [3, 10]");
+    if (r < 1 || r > m - 1)
+        return fail(RM_E_INVAL, "r must be in [1, m-1]");
+    if (P < 1 || P > 1024)
+        return fail(RM_E_INVAL, "P must be in [1, 1024]");
+    if (!(L == 1 || L == 2 || L == 4 || L == 8))
+        return fail(RM_E_INVAL, "L must be 1, 2, 4 or 8");
+    if (perm_mode != RM_PERM_NONE && perm_mode != RM_PERM_PFHT)
+        return fail(RM_E_INVAL, "unknown perm_mode");
+    if (perm_mode == RM_PERM_NONE && L != 1)
+        return fail(RM_E_UNSUPPORTED, "perm_mode NONE needs L = 1");
+    return RM_OK;
+}
+
+int binom_sum(int m, int r)
+{
+    int k = 0, c = 1;
+    for (int i = 0; i <= r; i++) {
+        k += c;
+        c = c * (m - i) / (i + 1);
+    }
+    return k;
+}
+
+} // namespace
+
+struct rm_decoder {
+    rm_config cfg;
+    int N, K, nperm, maps_per_dec;
+    const KernelEntry *kern;
+    uint32_t *d_maps;
+    size_t table_bytes;
+    hipStream_t stream;
+    int device;
+};
+
+extern "C" {
+
+const char *rm_last_error(void) { return g_err.c_str(); }
+
+int rm_supported(int m, int r, int L, int perm_mode)
+{
+    if (check_params(m, r, 1, L, perm_mode) != RM_OK)
+        return 0;
+    return find_kernel(m, r, L) != nullptr;
+}
+
+int rm_perm_tables(int m, int r, int P, int L, uint64_t seed, int perm_mode, uint16_t *rows, uint16_t *b, int *mdim,
+                   int cap)
+{
+    int rc = check_params(m, r, P, L, perm_mode);
+    if (rc != RM_OK)
+        return rc;
+    if (!rows || !b || !mdim)
+        return fail(RM_E_INVAL, "null output array");
+    const Draw d = draw_all(m, r, P, L, seed, perm_mode == RM_PERM_PFHT);
+    const int total = P * (L + d.nperm * 2 * L);
+    if (cap < total)
+        return fail(RM_E_INVAL, "cap too small: need " + std::to_string(total));
+    int k = 0;
+    auto put = [&](const Affine &a) {
+        for (int j = 0; j < 16; j++)
+            rows[k * 16 + j] = (uint16_t)(j < a.m ? a.row[j] : 0);
+        b[k] = (uint16_t)a.b;
+        mdim[k] = a.m;
+        k++;
+    };
+    for (int p = 0; p < P; p++) {
+        for (int l = 0; l < L; l++)
+            put(d.init[(size_t)p * L + l]);
+        for (int v = 0; v < d.nperm; v++)
+            for (int c = 0; c < 2 * L; c++)
+                put(d.cand[((size_t)p * d.nperm + v) * 2 * L + c]);
+    }
+    return k;
+}
+
+rm_decoder *rm_decoder_create_ex(const rm_config *cfg)
+{
+    if (!cfg) {
+        fail(RM_E_INVAL, "null config");
+        return nullptr;
+    }
+    if (check_params(cfg->m, cfg->r, cfg->P, cfg->L, cfg->perm_mode) != RM_OK)
+        return nullptr;
+    if (cfg->waves_per_block < 0 || cfg->waves_per_block > 4) {
+        fail(RM_E_INVAL, "waves_per_block must be in [0, 4]");
+        return nullptr;
+    }
+    const KernelEntry *k = find_kernel(cfg->m, cfg->r, cfg->L);
+    if (!k) {
+        fail(RM_E_UNSUPPORTED, "no kernel built for this (m, r, L)");
+        return nullptr;
+    }
+    const int m = cfg->m, r = cfg->r, P = cfg->P, L = cfg->L;
+    const int pfht = cfg->perm_mode == RM_PERM_PFHT;
+    const Draw d = draw_all(m, r, P, L, cfg->seed, pfht);
+    const int mpd = 2 * L + 4 * L * d.nperm;
+
+    // Per decoder: [0,L) initial maps, [L,2L) their inverses; for spine node v:
+    // [2L+4Lv, 2L+4Lv+2L) candidate maps (at v = 0 composed after the initial
+    // map of path c mod L), then their inverses.
+    std::vector<uint32_t> host((size_t)P * mpd * kMapWords);
+    for (int p = 0; p < P; p++) {
+        uint32_t *base = host.data() + (size_t)p * mpd * kMapWords;
+        std::vector<std::vector<uint32_t>> init_q(L);
+        for (int l = 0; l < L; l++) {
+            init_q[l] = table_of(d.init[(size_t)p * L + l]);
+            store_table(init_q[l], m, base + (size_t)l * kMapWords);
+            store_table(inverse_of(init_q[l]), m, base + (size_t)(L + l) * kMapWords);
+        }
+        for (int v = 0; v < d.nperm; v++) {
+            const int md = m - v;
+            for (int c = 0; c < 2 * L; c++) {
+                std::vector<uint32_t> q = table_of(d.cand[((size_t)p * d.nperm + v) * 2 * L + c]);
+                if (v == 0) {
+                    const std::vector<uint32_t> &pi = init_q[c % L];
+                    for (uint32_t &e : q)
+                        e = pi[e];
+                }
+                store_table(q, md, base + (size_t)(2 * L + 4 * L * v + c) * kMapWords);
+                store_table(inverse_of(q), md, base + (size_t)(2 * L + 4 * L * v + 2 * L + c) * kMapWords);
+            }
+        }
+    }
+
+    rm_decoder *dec = new (std::nothrow) rm_decoder();
+    if (!dec) {
+        fail(RM_E_NOMEM, "host allocation failed");
+        return nullptr;
+    }
+    dec->cfg = *cfg;
+    dec->N = 1 << m;
+    dec->K = binom_sum(m, r);
+    dec->nperm = d.nperm;
+    dec->maps_per_dec = mpd;
+    dec->kern = k;
+    dec->stream = nullptr;
+    dec->table_bytes = host.size() * sizeof(uint32_t);
+    int wpb = cfg->waves_per_block;
+    if (wpb == 0) {
+        wpb = 65536 / k->lds_bytes_per_wave;
+        wpb = wpb < 1 ? 1 : (wpb > 4 ? 4 : wpb);
+    }
+    if ((size_t)wpb * k->lds_bytes_per_wave > 65536) {
+        delete dec;
+        fail(RM_E_UNSUPPORTED, "LDS slice does not fit the requested waves per block");
+        return nullptr;
+    }
+    dec->cfg.waves_per_block = wpb;
+    hipError_t e = hipGetDevice(&dec->device);
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&dec->d_maps, dec->table_bytes);
+    if (e == hipSuccess)
+        e = hipMemcpy(dec->d_maps, host.data(), dec->table_bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        fail(RM_E_HIP, std::string("HIP error at create: ") + hipGetErrorString(e));
+        if (dec->d_maps)
+            (void)hipFree(dec->d_maps);
+        delete dec;
+        return nullptr;
+    }
+    g_err.clear();
+    return dec;
+}
+
+rm_decoder *rm_decoder_create(int m, int r, int P, int L, uint64_t seed)
+{
+    rm_config c{m, r, P, L, seed, RM_PERM_PFHT, 0};
+    return rm_decoder_create_ex(&c);
+}
+
+void rm_decoder_destroy(rm_decoder *d)
+{
+    if (!d)
+        return;
+    (void)hipStreamSynchronize(d->stream);
+    (void)hipFree(d->d_maps);
+    delete d;
+}
+
+int rm_decoder_set_stream(rm_decoder *d, void *hip_stream)
+{
+    if (!d)
+        return fail(RM_E_INVAL, "null decoder");
+    d->stream = (hipStream_t)hip_stream;
+    return RM_OK;
+}
+
+int rm_decoder_info(const rm_decoder *d, rm_info *out)
+{
+    if (!d || !out)
+        return fail(RM_E_INVAL, "null argument");
+    out->m = d->cfg.m;
+    out->r = d->cfg.r;
+    out->P = d->cfg.P;
+    out->L = d->cfg.L;
+    out->N = d->N;
+    out->K = d->K;
+    out->perm_mode = d->cfg.perm_mode;
+    out->n_perm_nodes = d->nperm;
+    out->maps_per_decoder = d->maps_per_dec;
+    out->waves_per_block = d->cfg.waves_per_block;
+    out->lds_bytes_per_wave = (size_t)d->kern->lds_bytes_per_wave;
+    out->table_bytes = d->table_bytes;
+    return RM_OK;
+}
+
+static int check_device_ptr(const void *p, const char *name)
+{
+    hipPointerAttribute_t a;
+    memset(&a, 0, sizeof a);
+    hipError_t e = hipPointerGetAttributes(&a, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(RM_E_PTR, std::string(name) + " is not device memory");
+    }
+    if (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged)
+        return fail(RM_E_PTR, std::string(name) + " is not device memory");
+    return RM_OK;
+}
+
+int rm_decode_batch(rm_decoder *d, const float *llr, int64_t n_frames, uint8_t *out_bits, float *out_metric)
+{
+    if (!d)
+        return fail(RM_E_INVAL, "null decoder");
+    if (n_frames < 0)
+        return fail(RM_E_INVAL, "n_frames < 0");
+    if (n_frames == 0)
+        return RM_OK;
+    if (!llr || !out_bits)
+        return fail(RM_E_INVAL, "null llr or out_bits");
+    int rc = check_device_ptr(llr, "llr");
+    if (rc == RM_OK)
+        rc = check_device_ptr(out_bits, "out_bits");
+    if (rc == RM_OK && out_metric)
+        rc = check_device_ptr(out_metric, "out_metric");
+    if (rc != RM_OK)
+        return rc;
+    KernelArgs a;
+    a.llr = llr;
+    a.out_bits = out_bits;
+    a.out_pm = out_metric;
+    a.maps = d->d_maps;
+    a.n_frames = n_frames;
+    a.P = d->cfg.P;
+    a.maps_per_dec = d->maps_per_dec;
+    a.pfht = d->cfg.perm_mode == RM_PERM_PFHT;
+    a.waves = d->cfg.waves_per_block;
+    const int64_t blocks64 = (n_frames + a.waves - 1) / a.waves;
+    const int blocks = (int)(blocks64 > (1 << 30) ? (1 << 30) : blocks64);
+    hipError_t e = d->kern->launch(a, blocks, d->stream);
+    if (e != hipSuccess)
+        return fail(RM_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return RM_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,181 @@
+"""Parity of the HIP decoder with the CPU oracle, through the C ABI.
+
+Every case decodes the same seeded synthetic frames on the GPU and with the
+oracle and requires identical codewords (bit-exact) and final metrics within
+1e-5 relative (both follow one operation order, so they are expected to be
+equal).  Sizes span several waves and a ragged tail; the full-size launch of
+the benchmark is checked on sampled frames and by code membership of every
+frame.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2108_12550_amd as rmd
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+NONE, PFHT = rmd.RM_PERM_NONE, rmd.RM_PERM_PFHT
+THREADS = min(16, os.cpu_count() or 1)
+PM_RTOL = 1e-5
+
+
+def gpu_decode(m, r, P, L, seed, mode, llr, waves=0):
+    dec = rmd.Decoder(m, r, P, L, seed=seed, perm_mode=mode, waves_per_block=waves)
+    t = torch.from_numpy(np.ascontiguousarray(llr)).cuda()
+    bits, pm = dec.decode(t)
+    torch.cuda.synchronize()
+    out = bits.cpu().numpy(), pm.cpu().numpy()
+    dec.close()
+    return out
+
+
+def oracle_decode(m, r, P, L, seed, mode, llr):
+    od = oracle.OracleDecoder(m, r, P, L, seed=seed, perm_mode=mode)
+    return od.decode_batch(llr, n_threads=THREADS)
+
+
+def assert_parity(got, ref, label):
+    gb, gp = got
+    rb, rp = ref
+    bad = np.nonzero(np.any(gb != rb, axis=1))[0]
+    assert bad.size == 0, f"{label}: {bad.size} frames differ in bits, first {bad[:8]}"
+    rel = np.abs(gp.astype(np.float64) - rp) / np.maximum(1.0, np.abs(rp))
+    assert rel.max() <= PM_RTOL, f"{label}: metric rel diff {rel.max()}"
+
+
+def check(m, r, P, L, mode, llr, seed=0, waves=0):
+    label = f"RM({r},{m}) P={P} L={L} mode={mode} seed={seed} n={llr.shape[0]}"
+    print("case", label, flush=True)
+    assert_parity(gpu_decode(m, r, P, L, seed, mode, llr, waves), oracle_decode(m, r, P, L, seed, mode, llr), label)
+
+
+# --- the benchmark configurations, at sizes the oracle finishes in seconds ---
+
+def test_plain_fht_fsc_rm27_all_frames():
+    _, llr = synth.frames(7, 2, 10000, 3.0, seed=0)
+    check(7, 2, 1, 1, NONE, llr)
+
+
+@pytest.mark.parametrize("ebn0", [2.0, 3.0, 4.0])
+def test_rm29_p20_l4(ebn0):
+    _, llr = synth.frames(9, 2, 197, ebn0, seed=11)
+    check(9, 2, 20, 4, PFHT, llr, seed=5)
+
+
+def test_rm29_p512_l1():
+    _, llr = synth.frames(9, 2, 21, 2.5, seed=12)
+    check(9, 2, 512, 1, PFHT, llr, seed=6)
+
+
+@pytest.mark.parametrize("ebn0", [2.0, 3.5])
+def test_rm38_p8_l8(ebn0):
+    _, llr = synth.frames(8, 3, 131, ebn0, seed=13)
+    check(8, 3, 8, 8, PFHT, llr, seed=7)
+
+
+@pytest.mark.parametrize("m,P", [(7, 8), (8, 16), (10, 32)])
+def test_mixed_codes_l4(m, P):
+    n = 67
+    e = synth.uniform_ebn0(n, 2.0, 4.0, seed=m)
+    _, llr = synth.frames(m, 2, n, e, seed=m)
+    check(m, 2, P, 4, PFHT, llr, seed=m)
+
+
+# --- the tree shapes and list sizes ---
+
+@pytest.mark.parametrize("m,r", [(4, 2), (5, 2), (6, 2), (5, 3), (6, 3), (7, 3), (8, 2), (9, 2)])
+@pytest.mark.parametrize("L", [1, 2, 4, 8])
+def test_codes_and_lists(m, r, L):
+    _, llr = synth.frames(m, r, 70, 1.0, seed=100 + m * 10 + r)
+    check(m, r, 3, L, PFHT, llr, seed=L)
+
+
+@pytest.mark.parametrize("m,r,L", [(3, 1, 1), (3, 1, 4), (4, 1, 4), (5, 1, 1), (6, 1, 4), (3, 2, 1), (3, 2, 4),
+                                   (4, 3, 4), (5, 4, 1), (5, 4, 4)])
+def test_leaf_roots(m, r, L):
+    _, llr = synth.frames(m, r, 65, 0.5, seed=200 + m)
+    check(m, r, 2, L, PFHT, llr, seed=3)
+
+
+def test_plain_mode_other_codes():
+    for m, r in [(5, 2), (8, 3), (9, 2)]:
+        _, llr = synth.frames(m, r, 40, 2.0, seed=300 + m)
+        check(m, r, 1, 1, NONE, llr)
+
+
+# --- ties: integer-valued and all-zero LLRs exercise every tie-break rule ---
+
+@pytest.mark.parametrize("m,r,P,L", [(5, 2, 2, 4), (7, 2, 3, 4), (8, 3, 2, 8), (9, 2, 4, 4), (6, 3, 2, 2),
+                                     (9, 2, 3, 1)])
+def test_integer_llr_ties(m, r, P, L):
+    rng = np.random.default_rng(m * 100 + L)
+    llr = rng.integers(-3, 4, size=(50, 1 << m)).astype(np.float32)
+    check(m, r, P, L, PFHT, llr, seed=1)
+
+
+def test_all_zero_llr():
+    llr = np.zeros((9, 512), np.float32)
+    check(9, 2, 4, 4, PFHT, llr, seed=2)
+
+
+def test_noiseless_frames_decode_to_sent_codeword():
+    x, _ = synth.frames(9, 2, 64, 3.0, seed=9)
+    llr = (8.0 * (1.0 - 2.0 * x)).astype(np.float32)
+    bits, pm = gpu_decode(9, 2, 20, 4, 0, PFHT, llr)
+    assert np.array_equal(synth.unpack_bits(bits, 512), x)
+    assert np.all(pm == 0.0)
+
+
+# --- launch shape: results must not depend on waves per block or batch size ---
+
+@pytest.mark.parametrize("waves", [1, 2, 3])
+def test_tile_invariance(waves):
+    _, llr = synth.frames(9, 2, 37, 2.5, seed=21)
+    ref = gpu_decode(9, 2, 20, 4, 4, PFHT, llr, waves=0)
+    got = gpu_decode(9, 2, 20, 4, 4, PFHT, llr, waves=waves)
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+    one = gpu_decode(9, 2, 20, 4, 4, PFHT, llr[5:6], waves=waves)
+    assert np.array_equal(one[0][0], ref[0][5]) and one[1][0] == ref[1][5]
+
+
+def test_empty_batch_is_noop():
+    dec = rmd.Decoder(9, 2, 20, 4)
+    t = torch.zeros((0, 512), device="cuda")
+    bits, pm = dec.decode(t)
+    torch.cuda.synchronize()
+    assert bits.shape == (0, 64) and pm.shape == (0,)
+
+
+def test_host_pointer_rejected():
+    dec = rmd.Decoder(7, 2, 1, 1, perm_mode=NONE)
+    llr = np.zeros((4, 128), np.float32)
+    out = np.zeros((4, 16), np.uint8)
+    rc = rmd.rm_decode_batch(dec._h, llr.ctypes.data, 4, out.ctypes.data, None)
+    assert rc == rmd.RM_E_PTR
+
+
+# --- the benchmark's full-size launch ---
+
+def test_full_size_rm29_p20_l4_sampled():
+    n = 262144
+    x, llr = synth.frames(9, 2, n, 3.0, seed=1)
+    print("case full-size RM(2,9) P=20 L=4 n=262144", flush=True)
+    bits, pm = gpu_decode(9, 2, 20, 4, 0, PFHT, llr)
+    # every output is a codeword: its syndrome against RM(m-r-1, m), the dual code, is zero
+    h = torch.from_numpy(synth.monomial_table(9, 9 - 2 - 1).astype(np.float32)).cuda()
+    xb = torch.from_numpy(synth.unpack_bits(bits, 512).astype(np.float32)).cuda()
+    syn = torch.remainder(xb @ h.T, 2.0)
+    assert int(syn.sum().item()) == 0
+    # sampled frames against the oracle, one by one
+    rng = np.random.default_rng(0)
+    idx = np.sort(rng.choice(n, 48, replace=False))
+    rb, rp = oracle_decode(9, 2, 20, 4, 0, PFHT, llr[idx])
+    assert_parity((bits[idx], pm[idx]), (rb, rp), "full-size sample")
