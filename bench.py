@@ -1,0 +1,197 @@
+"""Throughput benchmark of the batched p-FHT-FSCL-L-M decoder on one MI355X.
+
+Workload: RM(2,9) (N = 512, K = 46), P = 20 permuted decoders of list size
+L = 4 per frame, BPSK/AWGN frames at Eb/N0 = 2.0, 2.5, 3.0, 3.5, 4.0 dB,
+262,144 frames per Eb/N0 point.  One step decodes one point's batch (one
+kernel launch); steps cycle through the points.  All inputs are generated
+(seeded, synthetic) and copied to HBM before the timed region.
+
+Prints one JSON line.  Diagnostics go to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "frames/s & info Gbit/s, RM(9,2) 20×L4 FHT-FSCL; serving p50/p99 latency"
+M, R, P, L = 9, 2, 20, 4
+FRAMES = 262144
+EBN0 = [2.0, 2.5, 3.0, 3.5, 4.0]
+SEED = 0
+# Algorithmic work per frame: the paper's normalised complexity of
+# p-FHT-FSCL-4-20 on RM(2,9), floating-point additions and comparisons
+# (Table 5).  Per-op peak: 256 CUs x 64 lanes x 2.4 GHz, one non-packed FP32
+# add/min/compare per lane per clock.
+OPS_PER_FRAME = 4.2e5
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0
+KERNEL_NAME = "rm_decode_kernel<9, 2, 4>"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rm_decode_rm29_p20_l4_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2108_12550_amd", "csrc", f)
+                  for f in ("rmdec_device.hpp", "rmdec_kernels.hpp", "rmdec_inst_a.hip")]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter runs, or None
+    if they were taken on a different version of the kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(llr_host: np.ndarray, gpu_bits: np.ndarray, budget_s: float, threads: int):
+    """The CPU oracle on a bounded sample of the same frames."""
+    import oracle
+    od = oracle.OracleDecoder(M, R, P, L, seed=SEED)
+    chunk = 64 * threads
+    done = 0
+    t0 = time.perf_counter()
+    same = True
+    while done < llr_host.shape[0] and time.perf_counter() - t0 < budget_s:
+        sl = slice(done, min(done + chunk, llr_host.shape[0]))
+        bits, _ = od.decode_batch(llr_host[sl], n_threads=threads)
+        same &= bool(np.array_equal(bits, gpu_bits[sl]))
+        done = sl.stop
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "frames/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {done} frames of the 3.0 dB batch ({dt:.1f} s), {threads} threads, "
+                      f"bit-exact vs GPU: {same}"}, same
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--frames", type=int, default=FRAMES)
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for cpu_baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (for HBM counter scaling)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); frames are independent, "
+              "so N GPUs would each run this same launch on their share of the frames.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2108_12550_amd as rmd
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    K = synth.code_dimension(M, R)
+    n = args.frames
+    log(f"generating {len(EBN0)} x {n} frames of RM({R},{M})")
+    t0 = time.perf_counter()
+    batches = []
+    for k, e in enumerate(EBN0):
+        x, llr = synth.frames(M, R, n, e, seed=1000 + k)
+        batches.append((x, llr, torch.from_numpy(llr).to(dev)))
+    log(f"inputs ready in {time.perf_counter() - t0:.1f} s")
+
+    dec = rmd.Decoder(M, R, P, L, seed=SEED)
+    stream = torch.cuda.Stream(device=dev)
+    outs = [(torch.empty((n, 64), dtype=torch.uint8, device=dev), torch.empty((n,), dtype=torch.float32, device=dev))
+            for _ in EBN0]
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        with torch.cuda.stream(stream):
+            dst.copy_(src)
+        stream.synchronize()
+        log("copy calibration: 1 GiB read + 1 GiB written")
+
+    def step(i):
+        b = i % len(EBN0)
+        dec.decode(batches[b][2], out_bits=outs[b][0], out_metric=outs[b][1], stream=stream)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    ev0.record(stream)
+    for i in range(args.steps):
+        step(args.warmup + i)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    ms_total = ev0.elapsed_time(ev1)
+    ms_per_step = ms_total / max(1, args.steps)
+    fps = n / (ms_per_step / 1e3)
+
+    # frame error rate per point (from the last decode of each point)
+    fer = {}
+    for k, e in enumerate(EBN0):
+        xb = synth.unpack_bits(outs[k][0].cpu().numpy(), 1 << M)
+        fer[str(e)] = float(np.mean(np.any(xb != batches[k][0], axis=1)))
+    log(f"FER per Eb/N0: {fer}")
+
+    ops_per_launch = OPS_PER_FRAME * n
+    achieved = ops_per_launch / (ms_per_step / 1e3) / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(ALU_PEAK_TOPS, 4), "unit": "TFLOP/s",
+            "frac": round(achieved / ALU_PEAK_TOPS, 5), "traffic": measured_traffic(),
+            "kernel": KERNEL_NAME, "avg_launch_ms": round(ms_per_step, 4),
+            "hbm_gbs_algorithmic": round((4 * 512 + 64 + 4) * fps / 1e9, 2)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        gpu_bits = outs[EBN0.index(3.0)][0].cpu().numpy()
+        threads = min(16, os.cpu_count() or 1)
+        cpu, same = cpu_baseline(batches[EBN0.index(3.0)][1], gpu_bits, args.cpu_budget, threads)
+        log(f"cpu_baseline: {cpu}")
+
+    out = {
+        "metric": METRIC, "value": round(fps, 1), "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"RM(9,2) N=512 K=46 (paper's RM(2,9)), P=20 permuted decoders, L=4, "
+                               f"p-FHT-FSCL, BPSK/AWGN Eb/N0 2.0-4.0 dB step 0.5",
+                   "frames_per_step": n, "ebn0_db": EBN0, "seed": SEED},
+        "info_gbit_s": round(fps * K / 1e9, 4),
+        "wall_s_timed": round(wall, 3),
+        "fer": fer,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,23 +1,30 @@
 // rmdec_device.hpp -- gfx950 device code of the batched p-FHT-FSCL-L-M decoder.
 //
 // One wavefront decodes one frame at a time: it runs the P decoders of the
-// frame one after another (Alg. 5) and keeps the best (smallest final metric)
-// codeword.  Each decoder walks the Plotkin tree of RM(r,m) (Alg. 2), fully
-// unrolled at compile time from (m, r, L).  Node LLRs and partial codewords
-// live in the wave's LDS slice; the heavy per-node arithmetic (FHT, metric
-// reductions, top-k selection) runs in registers in a "row layout": the L
-// paths of the list occupy L groups of G = 64/L lanes, and element i of a
-// path sits in lane (i mod G) of its group, register i div G.
+// frame one after another (Alg. 5) and keeps the codeword with the smallest
+// final metric.  Each decoder walks the Plotkin tree of RM(r,m) (Alg. 2),
+// unrolled at compile time from (m, r, L).
 //
-// Every floating-point operation that can round is evaluated in the same
-// order as the CPU oracle: halving-tree sums (v[i] += v[i+w], w = n/2..1),
-// FHT butterflies with strides 2^{s-1}..1 computing (hi - lo, hi + lo),
-// g = b +/- a, and the printed metric updates left to right.  Build with
+// Row layout.  The L paths of the list occupy L groups of G = 64/L lanes.
+// Element i of a path's node vector sits in lane (i mod G) of the path's
+// group, register (i div G); a node of size n < G uses the first n lanes of
+// each group.  Node LLRs, FHT values and codeword bits (one bit per register,
+// packed in a mask per lane) stay in registers through the tree.  Moving a
+// surviving path's data to its list slot is one ds_bpermute per register.
+// LDS holds the frame's channel LLRs (read through the affine permutations),
+// the decoder's maps and small per-node scratch.
+//
+// Every rounding operation follows the CPU oracle's order: halving-tree sums
+// (v[i] += v[i+w], w = n/2..1; a lane butterfly gives every lane the same
+// value), FHT butterflies with strides 2^{s-1}..1 computing (hi - lo, hi + lo),
+// g = b -/+ a, and the metric updates left to right.  Build with
 // -ffp-contract=off.  Ties are broken by enumeration order everywhere.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 namespace rmdec {
 
@@ -40,12 +47,12 @@ struct KernelArgs {
 };
 
 // ---------------------------------------------------------------------------
-// small helpers
+// lane primitives
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
 
 // Orders this wave's LDS traffic: every lane's earlier LDS writes are visible
-// to every lane's later LDS reads.
+// to every lane's later LDS reads, and no access moves across it.
 __device__ __forceinline__ void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -53,43 +60,137 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ float shfl_xor_f(float v, int mask) { return __shfl_xor(v, mask, kWave); }
-
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask)
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp(uint32_t v)
 {
-    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, mask, kWave);
-    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), mask, kWave);
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+}
+
+// max/min of two doubles known to be ordinary (non-NaN) numbers; written as
+// instructions so that no quieting of signalling NaNs is added around them
+__device__ __forceinline__ double dmax(double a, double b)
+{
+    double r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ double dmin(double a, double b)
+{
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+// value held by lane (lane ^ W), W < 64
+template <int W>
+__device__ __forceinline__ uint32_t xor_lanes_u32(uint32_t v)
+{
+    if constexpr (W == 1)
+        return dpp<0xB1>(v); // quad_perm [1,0,3,2]
+    else if constexpr (W == 2)
+        return dpp<0x4E>(v); // quad_perm [2,3,0,1]
+    else if constexpr (W == 4)
+        return dpp<0x1B>(dpp<0x141>(v)); // row_half_mirror (^7), then quad_perm [3,2,1,0] (^3)
+    else if constexpr (W == 8)
+        return dpp<0x128>(v); // row_ror:8
+    else if constexpr (W == 16)
+        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F); // bit mode: xor 0x10
+    else
+        return (uint32_t)__builtin_amdgcn_ds_bpermute((lane_id() ^ W) << 2, (int)v);
+}
+
+template <int W>
+__device__ __forceinline__ float xor_lanes(float v)
+{
+    return __uint_as_float(xor_lanes_u32<W>(__float_as_uint(v)));
+}
+
+template <int W>
+__device__ __forceinline__ uint64_t xor_lanes(uint64_t v)
+{
+    const uint32_t lo = xor_lanes_u32<W>((uint32_t)v);
+    const uint32_t hi = xor_lanes_u32<W>((uint32_t)(v >> 32));
     return ((uint64_t)hi << 32) | lo;
 }
 
-__device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b) { return a > b ? a : b; }
+template <int W>
+__device__ __forceinline__ double xor_lanes(double v)
+{
+    return __longlong_as_double((long long)xor_lanes<W>((uint64_t)__double_as_longlong(v)));
+}
 
-// min-sum check-node update f(a,b) = sgn(a) sgn(b) min(|a|,|b|): the value
-// sgn(a) b clamped to [-|a|, |a|].  Equal to the textbook form except for the
-// sign of a zero result, which no later step can observe.
+// value held by lane `src`
+__device__ __forceinline__ uint32_t from_lane(uint32_t v, int src)
+{
+    return (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)v);
+}
+__device__ __forceinline__ float from_lane(float v, int src) { return __uint_as_float(from_lane(__float_as_uint(v), src)); }
+__device__ __forceinline__ int from_lane(int v, int src) { return (int)from_lane((uint32_t)v, src); }
+__device__ __forceinline__ uint64_t from_lane(uint64_t v, int src)
+{
+    return ((uint64_t)from_lane((uint32_t)(v >> 32), src) << 32) | from_lane((uint32_t)v, src);
+}
+
+// butterflies over aligned blocks of 2W lanes (W = 2^k or 0); every lane of
+// a block ends with the same value
+template <int W>
+__device__ __forceinline__ float bfly_sum(float v)
+{
+    if constexpr (W >= 1)
+        return bfly_sum<W / 2>(v + xor_lanes<W>(v));
+    else
+        return v;
+}
+template <int W>
+__device__ __forceinline__ double bfly_max(double v)
+{
+    if constexpr (W >= 1)
+        return bfly_max<W / 2>(dmax(v, xor_lanes<W>(v)));
+    else
+        return v;
+}
+template <int W>
+__device__ __forceinline__ uint64_t bfly_umax(uint64_t v)
+{
+    if constexpr (W >= 1) {
+        const uint64_t o = xor_lanes<W>(v);
+        return bfly_umax<W / 2>(o > v ? o : v);
+    } else {
+        return v;
+    }
+}
+template <int W>
+__device__ __forceinline__ uint32_t bfly_xor(uint32_t v)
+{
+    if constexpr (W >= 1)
+        return bfly_xor<W / 2>(v ^ xor_lanes_u32<W>(v));
+    else
+        return v;
+}
+
+// ---------------------------------------------------------------------------
+// check and bit node updates (Section II-B, min-sum)
+// ---------------------------------------------------------------------------
+// f(a,b) = sgn(a) sgn(b) min(|a|,|b|), computed as sgn(a) b clamped to
+// [-|a|, |a|]; it differs from the textbook form only in the sign of a zero
+// result, which no later step can observe.
 __device__ __forceinline__ float f_minsum(float a, float b)
 {
     const float sb = __uint_as_float(__float_as_uint(b) ^ (__float_as_uint(a) & 0x80000000u));
     return __builtin_amdgcn_fmed3f(sb, -fabsf(a), fabsf(a));
 }
 
-// bit-node update g(a,b,c) = b + (1-2c) a, one rounding
-__device__ __forceinline__ float g_func(float a, float b, uint32_t c) { return c ? (b - a) : (b + a); }
-
-// Affine map stored as columns: p(i) = b ^ XOR_{k: bit k of i} col[k].
-template <int MD>
-__device__ __forceinline__ uint32_t amap(const uint32_t *mp, uint32_t i)
+// g(a,b,c) = b + (1-2c) a, one rounding
+__device__ __forceinline__ float g_func(float a, float b, uint32_t c)
 {
-    uint32_t p = mp[kMapB];
-#pragma unroll
-    for (int k = 0; k < MD; k++)
-        p ^= ((i >> k) & 1u) ? mp[k] : 0u;
-    return p;
+    return b + __uint_as_float(__float_as_uint(a) ^ (c << 31));
 }
 
 // ---------------------------------------------------------------------------
-// compile-time shape of a code and of its per-wave LDS slice
+// compile-time shapes
 // ---------------------------------------------------------------------------
+__host__ __device__ constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
+
 __host__ __device__ constexpr int perm_spine(int m, int r)
 {
     int c = 0;
@@ -111,114 +212,107 @@ __host__ __device__ constexpr int max_spc_tau(int m, int r, int L)
 
 __host__ __device__ constexpr int align16(int x) { return (x + 15) & ~15; }
 
+template <int n, int G>
+struct Lay {
+    static constexpr int RR = n >= G ? n / G : 1; // registers per lane
+    static constexpr int ACT = n < G ? n : G;     // lanes of a group holding elements
+    using Mask = std::conditional_t<(RR > 32), uint64_t, uint32_t>;
+    static constexpr Mask FULL = RR >= 64 ? ~(Mask)0 : (Mask)(((uint64_t)1 << RR) - 1);
+};
+
 template <int M, int R, int L>
 struct Shape {
     static constexpr int N = 1 << M;
     static constexpr int G = kWave / L;
+    static constexpr int LG = ilog2(G);
     static constexpr int NPERM = perm_spine(M, R);
     static constexpr bool ROOT_LEAF = !(1 < R && R < M - 1);
     static constexpr int TAU = max_spc_tau(M, R, L);
     static constexpr int MAPS_PER_DEC = 2 * L + 4 * L * NPERM;
 
-    // level m' < M buffers hold L * 2^{m'} entries, offset L * (2^{m'} - 8)
-    static constexpr int LEVEL_ENTRIES = ROOT_LEAF ? 0 : L * (N - 8);
-    __host__ __device__ static constexpr int lvl(int m) { return L * ((1 << m) - 8); }
-
-    // byte offsets
+    // byte offsets of the per-wave LDS slice
     static constexpr int O_Y = 0;
-    static constexpr int O_ABUF = align16(O_Y + 4 * N);
-    static constexpr int O_AROOT = align16(O_ABUF + 4 * LEVEL_ENTRIES); // leaf roots only
-    static constexpr int O_PTMP = align16(O_AROOT + (ROOT_LEAF ? 4 * L * N : 0));
-    static constexpr int O_XL = align16(O_PTMP + (NPERM >= 2 ? 4 * L * N / 2 : 0));
-    static constexpr int O_XR = align16(O_XL + LEVEL_ENTRIES);
-    static constexpr int O_XPERM = align16(O_XR + LEVEL_ENTRIES);
-    static constexpr int O_XROOT = align16(O_XPERM + (NPERM >= 2 ? L * N / 2 : 0));
-    static constexpr int O_XBEST = align16(O_XROOT + L * N);
-    static constexpr int O_MAPS = align16(O_XBEST + N);
-    static constexpr int O_PML = align16(O_MAPS + 4 * kMapWords * MAPS_PER_DEC);
-    static constexpr int O_PMR = O_PML + 4 * (M + 1) * L;
-    static constexpr int O_PPM = O_PMR + 4 * (M + 1) * L;
-    static constexpr int O_ANCL = O_PPM + 4 * (M + 1) * L;
-    static constexpr int O_ANCR = O_ANCL + 4 * (M + 1) * L;
-    static constexpr int O_SEL = O_ANCR + 4 * (M + 1) * L;
-    static constexpr int O_LM = O_SEL + 4 * (M + 1) * 2 * L;
-    static constexpr int O_PMROOT = O_LM + 4 * 2 * L;
-    static constexpr int O_ANCROOT = O_PMROOT + 4 * L;
-    static constexpr int O_RMAP = O_ANCROOT + 4 * L;
-    static constexpr int O_ZERO = O_RMAP + 4 * L;
-    static constexpr int O_CPM = O_ZERO + 4 * L;          // FHTL candidates: L*L metrics
-    static constexpr int O_CINF = O_CPM + 4 * L * L;      // (index, sign) of each candidate
-    static constexpr int O_SLOT = O_CINF + 4 * L * L;     // survivors
-    static constexpr int O_FHTC = O_SLOT + 4 * L;         // per survivor: c word
-    static constexpr int O_FHTB = O_FHTC + 4 * L;         // per survivor: b0
-    static constexpr int O_ORD = O_FHTB + 4 * L;          // SPC: order[L][TAU+1]
-    static constexpr int O_SSRC = O_ORD + 4 * L * (TAU + 1);
-    static constexpr int O_SFLIP = O_SSRC + 4 * 2 * L;
-    static constexpr int O_SP = O_SFLIP + 4 * 2 * L;
-    static constexpr int O_SPM = O_SP + 4 * 2 * L;
-    static constexpr int O_CSRC = O_SPM + 4 * 2 * L;
-    static constexpr int O_CFLIP = O_CSRC + 4 * 2 * L;
-    static constexpr int O_CP = O_CFLIP + 4 * 2 * L;
-    static constexpr int O_CSPM = O_CP + 4 * 2 * L;
-    static constexpr int O_SFIX = O_CSPM + 4 * 2 * L;
-    static constexpr int O_BEST = O_SFIX + 4 * L;         // best metric, best inverse map word offset
-    static constexpr int BYTES = align16(O_BEST + 16);
+    static constexpr int O_MAPS = align16(O_Y + 4 * N);
+    static constexpr int O_STAGE = align16(O_MAPS + 4 * kMapWords * MAPS_PER_DEC); // spine nodes below the root
+    static constexpr int STAGE_BYTES = NPERM >= 2 ? 4 * L * N / 2 : 0;
+    static constexpr int O_CPM = align16(O_STAGE + STAGE_BYTES); // list merges: metrics
+    static constexpr int O_CINF = O_CPM + 4 * L * L;              // list merges: payload
+    static constexpr int O_CAUX = O_CINF + 4 * L * L;             // list merges: payload 2
+    static constexpr int O_SLOT = O_CAUX + 4 * L * L;             // survivors
+    static constexpr int O_SPCA = O_SLOT + 4 * L;                 // SPC: |alpha| at o_t [L][TAU+1]
+    static constexpr int O_SPCI = O_SPCA + 4 * L * (TAU + 1);     // SPC: o_t [L][TAU+1]
+    static constexpr int O_SPCP = O_SPCI + 4 * L * (TAU + 1);     // SPC: parity | hd(o_0) << 1
+    static constexpr int O_XBEST = align16(O_SPCP + 4 * L);       // winner's codeword masks, 2G words
+    static constexpr int BYTES = align16(O_XBEST + 16 * G);
 };
 
-// Pointers into one wave's LDS slice.
+// Per-wave context.
 template <int M, int R, int L>
-struct Ws {
+struct Ctx {
     using S = Shape<M, R, L>;
     unsigned char *base;
-    __device__ explicit Ws(unsigned char *b) : base(b) {}
+    int lane, g, lg;
+    int pfht;
     __device__ float *y() const { return (float *)(base + S::O_Y); }
-    __device__ float *abuf(int m) const { return (float *)(base + S::O_ABUF) + S::lvl(m); }
-    __device__ float *aroot() const { return (float *)(base + S::O_AROOT); }
-    __device__ float *ptmp() const { return (float *)(base + S::O_PTMP); }
-    __device__ uint8_t *xl(int m) const { return base + S::O_XL + S::lvl(m); }
-    __device__ uint8_t *xr(int m) const { return base + S::O_XR + S::lvl(m); }
-    __device__ uint8_t *xperm() const { return base + S::O_XPERM; }
-    __device__ uint8_t *xroot() const { return base + S::O_XROOT; }
-    __device__ uint8_t *xbest() const { return base + S::O_XBEST; }
     __device__ uint32_t *maps() const { return (uint32_t *)(base + S::O_MAPS); }
-    __device__ float *pmL(int m) const { return (float *)(base + S::O_PML) + m * L; }
-    __device__ float *pmR(int m) const { return (float *)(base + S::O_PMR) + m * L; }
-    __device__ float *ppm(int m) const { return (float *)(base + S::O_PPM) + m * L; }
-    __device__ int *ancL(int m) const { return (int *)(base + S::O_ANCL) + m * L; }
-    __device__ int *ancR(int m) const { return (int *)(base + S::O_ANCR) + m * L; }
-    __device__ int *sel(int m) const { return (int *)(base + S::O_SEL) + m * 2 * L; }
-    __device__ float *lm() const { return (float *)(base + S::O_LM); }
-    __device__ float *pmroot() const { return (float *)(base + S::O_PMROOT); }
-    __device__ int *ancroot() const { return (int *)(base + S::O_ANCROOT); }
-    __device__ int *rmap() const { return (int *)(base + S::O_RMAP); }
-    __device__ float *zero() const { return (float *)(base + S::O_ZERO); }
+    __device__ float *stage() const { return (float *)(base + S::O_STAGE); }
     __device__ float *cpm() const { return (float *)(base + S::O_CPM); }
     __device__ uint32_t *cinf() const { return (uint32_t *)(base + S::O_CINF); }
+    __device__ uint32_t *caux() const { return (uint32_t *)(base + S::O_CAUX); }
     __device__ int *slot() const { return (int *)(base + S::O_SLOT); }
-    __device__ uint32_t *fhtc() const { return (uint32_t *)(base + S::O_FHTC); }
-    __device__ uint32_t *fhtb() const { return (uint32_t *)(base + S::O_FHTB); }
-    __device__ int *ord() const { return (int *)(base + S::O_ORD); }
-    __device__ int *ssrc() const { return (int *)(base + S::O_SSRC); }
-    __device__ uint32_t *sflip() const { return (uint32_t *)(base + S::O_SFLIP); }
-    __device__ int *sp() const { return (int *)(base + S::O_SP); }
-    __device__ float *spm() const { return (float *)(base + S::O_SPM); }
-    __device__ int *csrc() const { return (int *)(base + S::O_CSRC); }
-    __device__ uint32_t *cflip() const { return (uint32_t *)(base + S::O_CFLIP); }
-    __device__ int *cp() const { return (int *)(base + S::O_CP); }
-    __device__ float *cspm() const { return (float *)(base + S::O_CSPM); }
-    __device__ uint32_t *sfix() const { return (uint32_t *)(base + S::O_SFIX); }
-    __device__ float *bestpm() const { return (float *)(base + S::O_BEST); }
-    __device__ int *bestmap() const { return (int *)(base + S::O_BEST + 4); }
+    __device__ float *spca() const { return (float *)(base + S::O_SPCA); }
+    __device__ int *spci() const { return (int *)(base + S::O_SPCI); }
+    __device__ uint32_t *spcp() const { return (uint32_t *)(base + S::O_SPCP); }
+    __device__ uint64_t *xbest() const { return (uint64_t *)(base + S::O_XBEST); }
 };
 
+template <int n, int G>
+struct NodeRes {
+    typename Lay<n, G>::Mask x; // codeword bits of the path held by this group
+    float pm;                   // its metric
+    int anc;                    // input path it descends from
+};
+
+// Rank-based stable selection of the `keep` smallest of `cnt` metrics in
+// LDS (ties to the lower position): slot[r] receives the position of rank r.
+// slot[0..keep) must already hold valid positions.
+template <int cnt, int keep>
+__device__ __forceinline__ void select_smallest(const float *pm, int *slot, int lane)
+{
+    if (lane < cnt) {
+        const float my = pm[lane];
+        int rank = 0;
+#pragma unroll
+        for (int q = 0; q < cnt; q++) {
+            const float o = pm[q];
+            rank += (o < my) || (o == my && q < lane);
+        }
+        if (rank < keep)
+            slot[rank] = lane;
+    }
+}
+
+// Positions p(i) of elements i = lg + G j (j < RR) under an affine map on
+// F2^MD stored as columns: the lane part first, then one XOR per register.
+template <int MD, int G, int RR>
+__device__ __forceinline__ void map_positions(const uint32_t *mp, int lg, uint32_t (&pos)[RR])
+{
+    constexpr int LG = ilog2(G);
+    uint32_t base = mp[kMapB];
+#pragma unroll
+    for (int k = 0; k < LG && k < MD; k++)
+        base ^= ((lg >> k) & 1) ? mp[k] : 0u;
+    pos[0] = base;
+#pragma unroll
+    for (int j = 1; j < RR; j++)
+        pos[j] = pos[j & (j - 1)] ^ mp[LG + __builtin_ctz(j)];
+}
+
 // ---------------------------------------------------------------------------
-// canonical halving-tree sum of one value per element, row layout.
-// v[j] holds element i = lg + G*j (j < RR); the n-element sum ends in lane 0
-// of the group.  Lanes whose element is beyond n only feed lanes that are
-// never read.
+// canonical halving-tree sum over a node vector in row layout
 // ---------------------------------------------------------------------------
 template <int n, int G, int RR>
-__device__ __forceinline__ float tree_sum_rows(float (&v)[RR])
+__device__ __forceinline__ float tree_sum(float (&v)[RR])
 {
 #pragma unroll
     for (int w = n / 2; w >= G; w /= 2) {
@@ -226,47 +320,16 @@ __device__ __forceinline__ float tree_sum_rows(float (&v)[RR])
         for (int j = 0; j < w / G; j++)
             v[j] = v[j] + v[j + w / G];
     }
-    constexpr int top = (n < G ? n : G) / 2;
-#pragma unroll
-    for (int w = top; w >= 1; w /= 2)
-        v[0] = v[0] + shfl_xor_f(v[0], w);
-    return v[0];
+    return bfly_sum<Lay<n, G>::ACT / 2>(v[0]);
 }
 
-// ---------------------------------------------------------------------------
-// FHTL leaf, node RM(1, s): Alg. 3 over Alg. 4.
-// in:  a [L][n] LLRs, pm_in[L];  out: x [L][n] codeword bytes, pm_out, anc_out
-// ---------------------------------------------------------------------------
-template <int M, int R, int L, int S>
-__device__ void fhtl_leaf(const Ws<M, R, L> &w, const float *a, const float *pm_in, uint8_t *x, float *pm_out,
-                          int *anc_out)
+// FHT butterflies (Alg. 4): stride h = 2^{s-1} .. 1, (lo, hi) <- (hi - lo, hi + lo)
+template <int H, int G, int RR>
+__device__ __forceinline__ void fht_stages(float (&F)[RR], int lg)
 {
-    constexpr int n = 1 << S;
-    constexpr int G = kWave / L;
-    constexpr int RR = n >= G ? n / G : 1;
-    constexpr int K = L < n ? L : n;
-    const int lane = lane_id();
-    const int g = lane / G;
-    const int lg = lane % G;
-    const bool valid = (n >= G) || (lg < n);
-
-    float F[RR];
-    float v[RR];
-#pragma unroll
-    for (int j = 0; j < RR; j++) {
-        const int i = lg + G * j;
-        F[j] = valid ? a[g * n + i] : 0.0f;
-        v[j] = fabsf(F[j]);
-    }
-    // LLR_abs by the halving tree, broadcast from lane 0 of the group
-    const float sabs = __shfl(tree_sum_rows<n, G, RR>(v), 0, G);
-
-    // butterflies, stride h = 2^{s-1} .. 1: (lo, hi) <- (hi - lo, hi + lo)
-#pragma unroll
-    for (int t = 0; t < S; t++) {
-        const int h = 1 << (S - t - 1);
-        if (h >= G) {
-            const int hj = h / G;
+    if constexpr (H >= 1) {
+        if constexpr (H >= G) {
+            constexpr int hj = H / G;
 #pragma unroll
             for (int j = 0; j < RR; j++)
                 if ((j & hj) == 0) {
@@ -275,435 +338,515 @@ __device__ void fhtl_leaf(const Ws<M, R, L> &w, const float *a, const float *pm_
                     F[j + hj] = hi + lo;
                 }
         } else {
-            const bool upper = (lg & h) != 0;
+            // lower lane: partner - self = hi - lo; upper lane: partner + self = lo + hi
+            const uint32_t neg = (lg & H) ? 0u : 0x80000000u;
 #pragma unroll
             for (int j = 0; j < RR; j++) {
-                const float p = shfl_xor_f(F[j], h);
-                F[j] = upper ? (F[j] + p) : (p - F[j]);
+                const float p = xor_lanes<H>(F[j]);
+                F[j] = p + __uint_as_float(__float_as_uint(F[j]) ^ neg);
+            }
+        }
+        fht_stages<H / 2, G, RR>(F, lg);
+    }
+}
+
+// Walsh mask: bit j (j < RR) = parity(c & j)
+template <int RR, class MaskT>
+__device__ __forceinline__ MaskT walsh_mask(uint32_t c)
+{
+    constexpr uint64_t pat[6] = {0xAAAAAAAAAAAAAAAAull, 0xCCCCCCCCCCCCCCCCull, 0xF0F0F0F0F0F0F0F0ull,
+                                 0xFF00FF00FF00FF00ull, 0xFFFF0000FFFF0000ull, 0xFFFFFFFF00000000ull};
+    MaskT w = 0;
+#pragma unroll
+    for (int k = 0; k < ilog2(RR); k++)
+        w ^= ((c >> k) & 1u) ? (MaskT)pat[k] : (MaskT)0;
+    return w;
+}
+
+// FHT key: |F| widened to double, with (1024 - i, sign) in low mantissa bits
+// that the conversion leaves zero: a larger |F| wins, then the lower index.
+__device__ __forceinline__ double fht_key(float f, uint32_t i)
+{
+    const uint64_t d = (uint64_t)__double_as_longlong((double)fabsf(f));
+    return __longlong_as_double((long long)(d | (((1024u - i) << 1) | (f < 0.0f ? 1u : 0u))));
+}
+
+// ---------------------------------------------------------------------------
+// FHTL leaf RM(1,s): Alg. 3 over Alg. 4 with the metric of Eq. (10).
+// A: this group's path LLRs (row layout), pm: its metric.
+// ---------------------------------------------------------------------------
+template <int M, int R, int L, int S>
+__device__ __forceinline__ NodeRes<(1 << S), kWave / L> fhtl(const Ctx<M, R, L> &c,
+                                                              float (&A)[Lay<(1 << S), kWave / L>::RR], float pm)
+{
+    constexpr int n = 1 << S;
+    constexpr int G = kWave / L;
+    using Ly = Lay<n, G>;
+    constexpr int RR = Ly::RR;
+    constexpr int ACT = Ly::ACT;
+    constexpr int K = L < n ? L : n;
+    using MaskT = typename Ly::Mask;
+    const int lg = c.lg;
+    const bool valid = lg < ACT;
+
+    float v[RR];
+#pragma unroll
+    for (int j = 0; j < RR; j++)
+        v[j] = valid ? fabsf(A[j]) : 0.0f;
+    const float sabs = tree_sum<n, G, RR>(v); // LLR_abs
+
+    fht_stages<n / 2, G, RR>(A, lg);
+
+    // lane-local two largest keys
+    double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < RR; j++) {
+        const double k = valid ? fht_key(A[j], (uint32_t)(lg + G * j)) : 0.0;
+        const double lo = dmin(b1, k);
+        b1 = dmax(b1, k);
+        b2 = dmax(b2, lo);
+    }
+    bool b2ok = true;
+
+    // K rounds: the group's largest remaining key is the next candidate
+    float mypm = 0.0f;
+    uint32_t myinf = 0;
+#pragma unroll
+    for (int t = 0; t < K; t++) {
+        const double w = bfly_max<ACT / 2>(b1);
+        const uint64_t wb = (uint64_t)__double_as_longlong(w);
+        const float absf = (float)__longlong_as_double((long long)(wb & ~0x1FFFFFFFull));
+        const float cand = pm + 0.5f * (sabs - absf);
+        if (lg == t) {
+            mypm = cand;
+            myinf = (uint32_t)wb & 0xFFFu;
+        }
+        if (t + 1 < K) {
+            const bool own = valid && (b1 == w);
+            const bool need = own && !b2ok;
+            if (__any(need)) {
+                // the owner's second key was already used: rescan below w
+                double nb1 = 0.0, nb2 = 0.0;
+#pragma unroll
+                for (int j = 0; j < RR; j++) {
+                    double k = valid ? fht_key(A[j], (uint32_t)(lg + G * j)) : 0.0;
+                    k = k < w ? k : 0.0;
+                    const double lo = dmin(nb1, k);
+                    nb1 = dmax(nb1, k);
+                    nb2 = dmax(nb2, lo);
+                }
+                if (need) {
+                    b1 = nb1;
+                    b2 = nb2;
+                    b2ok = true;
+                }
+            }
+            if (own && !need) {
+                b1 = b2;
+                b2 = 0.0;
+                b2ok = false;
             }
         }
     }
 
-    // keys: |F| bits, then (1024 - i) so that lower indices win ties, then sign
+    // stable merge of the L*K candidates by metric, keep L (Alg. 3)
+    float *cpm = c.cpm();
+    uint32_t *cinf = c.cinf();
+    int *slot = c.slot();
+    if (lg < K) {
+        cpm[c.g * K + lg] = mypm;
+        cinf[c.g * K + lg] = myinf;
+    }
+    if (c.lane < L)
+        slot[c.lane] = c.lane;
+    wave_sync();
+    select_smallest<L * K, L>(cpm, slot, c.lane);
+    wave_sync();
+    const int e = slot[c.g];
+    const float opm = cpm[e];
+    const uint32_t inf = cinf[e];
+    wave_sync();
+
+    // codeword of transform index idx: x(z) = [F<0] ^ parity(cw) ^ parity(cw & z), cw = n-1-idx
+    const uint32_t idx = 1024u - (inf >> 1);
+    const uint32_t cw = (uint32_t)(n - 1) - idx;
+    const uint32_t b0 = (inf & 1u) ^ (__popc(cw) & 1u);
+    const uint32_t lbit = b0 ^ (__popc(cw & (uint32_t)lg) & 1u);
+    MaskT x;
+    if constexpr (n >= G)
+        x = (walsh_mask<RR, MaskT>(cw >> ilog2(G)) ^ (lbit ? ~(MaskT)0 : (MaskT)0)) & Ly::FULL;
+    else
+        x = (MaskT)lbit;
+    return {x, opm, e / K};
+}
+
+// ---------------------------------------------------------------------------
+// SPCL leaf RM(s-1,s): Eqs. (2)-(6), tau = min(L, 2^s - 1) splits (0 if L = 1)
+// ---------------------------------------------------------------------------
+template <int M, int R, int L, int S>
+__device__ __forceinline__ NodeRes<(1 << S), kWave / L> spcl(const Ctx<M, R, L> &c,
+                                                              float (&A)[Lay<(1 << S), kWave / L>::RR], float pm)
+{
+    constexpr int n = 1 << S;
+    constexpr int G = kWave / L;
+    using Ly = Lay<n, G>;
+    constexpr int RR = Ly::RR;
+    constexpr int ACT = Ly::ACT;
+    constexpr int tau = spc_tau(L, n);
+    constexpr int TS = Shape<M, R, L>::TAU + 1;
+    using MaskT = typename Ly::Mask;
+    const int lg = c.lg;
+    const int g = c.g;
+    const bool valid = lg < ACT;
+
+    // hard decisions and parity (Eq. (2))
+    MaskT hd = 0;
+#pragma unroll
+    for (int j = 0; j < RR; j++)
+        hd |= (valid && A[j] < 0.0f) ? ((MaskT)1 << j) : (MaskT)0;
+    const uint32_t par = bfly_xor<ACT / 2>((uint32_t)(__popcll((uint64_t)hd) & 1));
+
+    // o_0 .. o_tau: |alpha| ascending, ties to the lower index
     uint64_t key[RR];
 #pragma unroll
     for (int j = 0; j < RR; j++) {
         const uint32_t i = (uint32_t)(lg + G * j);
-        key[j] = valid ? (((uint64_t)__float_as_uint(fabsf(F[j])) << 32) | ((1024u - i) << 1) |
-                          (F[j] < 0.0f ? 1u : 0u))
-                       : 0ull;
+        key[j] = valid ? (((uint64_t)(0x7FFFFFFFu - __float_as_uint(fabsf(A[j]))) << 32) | (1024u - i)) : 0ull;
     }
-    float *cpm = w.cpm();
-    uint32_t *cinf = w.cinf();
-    const float pmg = pm_in[g];
-    for (int t = 0; t < K; t++) {
-        uint64_t best = key[0];
+    float *spca = c.spca();
+    int *spci = c.spci();
+#pragma unroll
+    for (int t = 0; t <= tau; t++) {
+        uint64_t b = key[0];
 #pragma unroll
         for (int j = 1; j < RR; j++)
-            best = umax64(best, key[j]);
-#pragma unroll
-        for (int m = (n < G ? n : G) / 2; m >= 1; m /= 2)
-            best = umax64(best, shfl_xor_u64(best, m));
+            b = key[j] > b ? key[j] : b;
+        const uint64_t w = bfly_umax<ACT / 2>(b);
 #pragma unroll
         for (int j = 0; j < RR; j++)
-            if (key[j] == best)
-                key[j] = 0ull;
+            key[j] = key[j] == w ? 0ull : key[j];
         if (lg == 0) {
-            const float absf = __uint_as_float((uint32_t)(best >> 32));
-            const uint32_t lo = (uint32_t)best;
-            cpm[g * K + t] = pmg + 0.5f * (sabs - absf);
-            cinf[g * K + t] = ((1024u - (lo >> 1)) << 1) | (lo & 1u);
+            spca[g * TS + t] = __uint_as_float(0x7FFFFFFFu - (uint32_t)(w >> 32));
+            spci[g * TS + t] = (int)(1024u - (uint32_t)w);
         }
     }
+    uint32_t *spcp = c.spcp();
     wave_sync();
+    const int o0 = spci[g * TS];
+    const float a0 = spca[g * TS];
+    const uint32_t hd_o0 = (uint32_t)(from_lane((uint64_t)hd, g * G + (o0 % G)) >> (o0 / G)) & 1u;
+    if (lg == 0)
+        spcp[g] = par | (hd_o0 << 1);
+    float cur = pm;
+    if (par) // Eq. (3)
+        cur = pm + a0;
 
-    // stable merge of the L*K candidates by metric; keep L
-    int *slot = w.slot();
-    if (lane < L)
-        slot[lane] = 0;
+    // state of the path held by this group
+    int src = g;
+    uint32_t flips = 0;
+    uint32_t p = par;
+    float *cpm = c.cpm();
+    uint32_t *cinf = c.cinf();
+    uint32_t *caux = c.caux();
+    int *slot = c.slot();
     wave_sync();
-    if (lane < L * K) {
-        const float my = cpm[lane];
-        int rank = 0;
-        for (int e = 0; e < L * K; e++) {
-            const float o = cpm[e];
-            rank += (o < my) || (o == my && e < lane);
-        }
-        if (rank < L)
-            slot[rank] = lane;
-    }
-    wave_sync();
-    uint32_t *fc = w.fhtc();
-    uint32_t *fb = w.fhtb();
-    if (lane < L) {
-        const int e = slot[lane];
-        const uint32_t inf = cinf[e];
-        const uint32_t idx = inf >> 1;
-        const uint32_t c = (uint32_t)(n - 1) - idx;
-        // codeword of transform index idx: x(z) = [F<0] ^ parity(c) ^ parity(c & z)
-        fc[lane] = c;
-        fb[lane] = (inf & 1u) ^ (__popc(c) & 1u);
-        pm_out[lane] = cpm[e];
-        anc_out[lane] = e / K;
-    }
-    wave_sync();
-    for (int e = lane; e < L * n; e += kWave) {
-        const int l = e / n;
-        const uint32_t z = (uint32_t)(e % n);
-        x[e] = (uint8_t)(fb[l] ^ (__popc(fc[l] & z) & 1u));
-    }
-    wave_sync();
-}
-
-// ---------------------------------------------------------------------------
-// SPCL leaf, node RM(s-1, s): Eqs. (2)-(6) with tau = min(L, n-1) splits.
-// ---------------------------------------------------------------------------
-template <int M, int R, int L, int S>
-__device__ void spcl_leaf(const Ws<M, R, L> &w, const float *a, const float *pm_in, uint8_t *x, float *pm_out,
-                          int *anc_out)
-{
-    constexpr int n = 1 << S;
-    constexpr int tau = spc_tau(L, n);
-    constexpr int TS = Shape<M, R, L>::TAU + 1; // stride of the order table
-    const int lane = lane_id();
-    int *ord = w.ord();
-    int *ssrc = w.ssrc();
-    uint32_t *sflip = w.sflip();
-    int *sp = w.sp();
-    float *spm = w.spm();
-
-    if (lane < L) {
-        const float *al = a + lane * n;
-        uint32_t p = 0;
-        for (int i = 0; i < n; i++)
-            p ^= al[i] < 0.0f ? 1u : 0u;
-        // the tau+1 least reliable positions, |alpha| ascending, ties to the lower index
-        float pv = -1.0f;
-        int pi = -1;
-        for (int t = 0; t <= tau; t++) {
-            float bv = 0.0f;
-            int bi = -1;
-            for (int i = 0; i < n; i++) {
-                const float av = fabsf(al[i]);
-                const bool after = (av > pv) || (av == pv && i > pi);
-                if (after && (bi < 0 || av < bv)) {
-                    bv = av;
-                    bi = i;
-                }
-            }
-            bi = bi < 0 ? 0 : bi; // only reachable with non-finite input
-            ord[lane * TS + t] = bi;
-            pv = bv;
-            pi = bi;
-        }
-        float pm = pm_in[lane];
-        if (p)
-            pm = pm + fabsf(al[ord[lane * TS]]);
-        ssrc[lane] = lane;
-        sflip[lane] = 0u;
-        sp[lane] = (int)p;
-        spm[lane] = pm;
-    }
-    wave_sync();
-
-    int *csrc = w.csrc();
-    uint32_t *cflip = w.cflip();
-    int *cp = w.cp();
-    float *cspm = w.cspm();
+#pragma unroll
     for (int t = 1; t <= tau; t++) {
-        if (lane < 2 * L) {
-            const int q = lane >> 1;
-            int src = ssrc[q];
-            uint32_t fl = sflip[q];
-            int p = sp[q];
-            float pm = spm[q];
-            if (lane & 1) {
-                const float at = fabsf(a[src * n + ord[src * TS + t]]);
-                const float a0 = fabsf(a[src * n + ord[src * TS]]);
-                pm = (pm + at) + (p ? -a0 : a0);
-                p ^= 1;
-                fl |= 1u << t;
-            }
-            csrc[lane] = src;
-            cflip[lane] = fl;
-            cp[lane] = p;
-            cspm[lane] = pm;
+        // (keep, flip o_t) for every path in list order; Eqs. (4) and (5)
+        const float at = spca[src * TS + t];
+        const float as0 = spca[src * TS];
+        const float fpm = (cur + at) + (p ? -as0 : as0);
+        if (lg < 2) {
+            const int e = 2 * g + lg;
+            cpm[e] = lg ? fpm : cur;
+            cinf[e] = (uint32_t)src | ((lg ? (p ^ 1u) : p) << 8);
+            caux[e] = lg ? (flips | (1u << t)) : flips;
         }
+        if (c.lane < L)
+            slot[c.lane] = c.lane;
         wave_sync();
-        if (lane < 2 * L) {
-            const float my = cspm[lane];
-            int rank = 0;
-            for (int e = 0; e < 2 * L; e++) {
-                const float o = cspm[e];
-                rank += (o < my) || (o == my && e < lane);
-            }
-            if (rank < L) {
-                ssrc[rank] = csrc[lane];
-                sflip[rank] = cflip[lane];
-                sp[rank] = cp[lane];
-                spm[rank] = cspm[lane];
-            }
-        }
+        select_smallest<2 * L, L>(cpm, slot, c.lane);
+        wave_sync();
+        const int e = slot[g];
+        cur = cpm[e];
+        src = (int)(cinf[e] & 0xFFu);
+        p = (cinf[e] >> 8) & 1u;
+        flips = caux[e];
         wave_sync();
     }
 
-    uint32_t *sfix = w.sfix();
-    if (lane < L) {
-        const int src = ssrc[lane];
-        const int o0 = ord[src * TS];
-        // parity of the hard decisions of the source path, flipped once per split taken
-        uint32_t p0 = 0;
-        for (int i = 0; i < n; i++)
-            p0 ^= a[src * n + i] < 0.0f ? 1u : 0u;
-        const uint32_t hd0 = a[src * n + o0] < 0.0f ? 1u : 0u;
-        sfix[lane] = p0 ^ (__popc(sflip[lane]) & 1u) ^ hd0; // Eq. (6)
-        pm_out[lane] = spm[lane];
-        anc_out[lane] = src;
+    // codeword: hard decisions of the source path, the taken flips, then the
+    // parity of o_0 (Eq. (6))
+    MaskT x = (MaskT)from_lane((uint64_t)hd, src * G + lg);
+    const uint32_t sp = spcp[src];
+    const int so0 = spci[src * TS];
+    const uint32_t fix = (sp & 1u) ^ (__popc(flips) & 1u) ^ ((sp >> 1) & 1u);
+#pragma unroll
+    for (int t = 1; t <= tau; t++) {
+        const int pos = spci[src * TS + t];
+        if (((flips >> t) & 1u) && (pos % G) == lg)
+            x ^= (MaskT)1 << (pos / G);
     }
+    if ((so0 % G) == lg)
+        x = (x & ~((MaskT)1 << (so0 / G))) | ((MaskT)fix << (so0 / G));
     wave_sync();
-    for (int e = lane; e < L * n; e += kWave) {
-        const int q = e / n;
-        const int i = e % n;
-        const int src = ssrc[q];
-        const uint32_t fl = sflip[q];
-        uint32_t bit = a[src * n + i] < 0.0f ? 1u : 0u;
-        for (int t = 1; t <= tau; t++)
-            if (((fl >> t) & 1u) && ord[src * TS + t] == i)
-                bit ^= 1u;
-        if (i == ord[src * TS])
-            bit = sfix[q];
-        x[e] = (uint8_t)bit;
-    }
-    wave_sync();
+    return {x, cur, src};
 }
 
 // ---------------------------------------------------------------------------
-// permutation-domain selection at a node of size 2^MD (Alg. 2): candidate c
-// reads path c mod L through map c; LM_c = sum_i |f|, halving tree; keep the
-// L largest (ties to the lower c).  Source element i of path l is src(l, i).
-// Writes sel[0..L) (candidate indices, rank order).
+// f and g steps in row layout: node of size n -> child of size n/2
+// ---------------------------------------------------------------------------
+template <int n, int G>
+__device__ __forceinline__ void f_step(const float (&A)[Lay<n, G>::RR], float (&C)[Lay<n / 2, G>::RR])
+{
+    constexpr int RR = Lay<n, G>::RR;
+    if constexpr (n / 2 >= G) {
+#pragma unroll
+        for (int j = 0; j < RR / 2; j++)
+            C[j] = f_minsum(A[j], A[j + RR / 2]);
+    } else {
+        C[0] = f_minsum(A[0], xor_lanes<n / 2>(A[0]));
+    }
+}
+
+template <int n, int G>
+__device__ __forceinline__ void g_step(const float (&A)[Lay<n, G>::RR], typename Lay<n / 2, G>::Mask xl,
+                                       float (&C)[Lay<n / 2, G>::RR])
+{
+    constexpr int RR = Lay<n, G>::RR;
+    if constexpr (n / 2 >= G) {
+#pragma unroll
+        for (int j = 0; j < RR / 2; j++)
+            C[j] = g_func(A[j], A[j + RR / 2], (uint32_t)(xl >> j) & 1u);
+    } else {
+        C[0] = g_func(A[0], xor_lanes<n / 2>(A[0]), (uint32_t)xl & 1u);
+    }
+}
+
+// x_nu = (x_gamma ^ x_lambda, x_gamma)
+template <int n, int G>
+__device__ __forceinline__ typename Lay<n, G>::Mask combine(typename Lay<n / 2, G>::Mask xl,
+                                                            typename Lay<n / 2, G>::Mask xr, int lg)
+{
+    using MaskT = typename Lay<n, G>::Mask;
+    if constexpr (n / 2 >= G) {
+        constexpr int H = Lay<n / 2, G>::RR;
+        return (MaskT)(xl ^ xr) | ((MaskT)xr << H);
+    } else {
+        const uint32_t up = xor_lanes_u32<n / 2>((uint32_t)xr);
+        return (MaskT)(lg < n / 2 ? ((uint32_t)(xl ^ xr) & 1u) : (up & 1u));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Permutation-domain selection at a node of size 2^MD (Alg. 2): candidate c
+// reads path c mod L through map c; LM_c = sum_i |f| over the halving tree;
+// the L largest survive (ties to the lower c).  src(path, position) reads the
+// node LLRs.  Returns the candidate that becomes this group's path.
 // ---------------------------------------------------------------------------
 template <int M, int R, int L, int MD, class Src>
-__device__ void perm_select(const Ws<M, R, L> &w, const uint32_t *cand_maps, Src src, int *sel)
+__device__ __forceinline__ int perm_select(const Ctx<M, R, L> &c, const uint32_t *cand_maps, Src src)
 {
     constexpr int n = 1 << MD;
     constexpr int h = n / 2;
     constexpr int G = kWave / L;
-    constexpr int RR = h >= G ? h / G : 1;
-    const int lane = lane_id();
-    const int g = lane / G;
-    const int lg = lane % G;
-    const bool valid = (h >= G) || (lg < h);
-    float *lm = w.lm();
+    using Lh = Lay<h, G>;
+    constexpr int RR = Lh::RR;
+    const bool valid = c.lg < Lh::ACT;
+    float lm[2];
 #pragma unroll
     for (int pass = 0; pass < 2; pass++) {
-        const int c = g + L * pass;
-        const uint32_t *mp = cand_maps + c * kMapWords;
+        const uint32_t *mp = cand_maps + (c.g + L * pass) * kMapWords;
+        uint32_t pos[RR];
+        map_positions<MD - 1, G, RR>(mp, c.lg, pos);
         const uint32_t colh = mp[MD - 1];
         float v[RR];
 #pragma unroll
-        for (int j = 0; j < RR; j++) {
-            const uint32_t i = (uint32_t)(lg + G * j);
-            float t = 0.0f;
-            if (valid) {
-                const uint32_t p = amap<MD>(mp, i);
-                const float x0 = src(g, p);
-                const float x1 = src(g, p ^ colh); // image of i + h
-                t = fminf(fabsf(x0), fabsf(x1));
-            }
-            v[j] = t;
-        }
-        const float s = tree_sum_rows<h, G, RR>(v);
-        if (lg == 0)
-            lm[c] = s;
+        for (int j = 0; j < RR; j++)
+            v[j] = valid ? fminf(fabsf(src(c.g, pos[j])), fabsf(src(c.g, pos[j] ^ colh))) : 0.0f;
+        lm[pass] = tree_sum<h, G, RR>(v);
     }
-    if (lane < L)
-        sel[lane] = lane; // keeps every entry a valid candidate even for non-finite LM
+    // rank of candidates g and g+L among all 2L (larger LM first, ties to lower index)
+    int r0 = 0, r1 = 0;
+#pragma unroll
+    for (int q = 0; q < L; q++) {
+        const float o0 = from_lane(lm[0], q * G);
+        const float o1 = from_lane(lm[1], q * G);
+        r0 += (o0 > lm[0]) || (o0 == lm[0] && q < c.g);
+        r0 += (o1 > lm[0]);
+        r1 += (o0 > lm[1]) || (o0 == lm[1]);
+        r1 += (o1 > lm[1]) || (o1 == lm[1] && q < c.g);
+    }
+    int *slot = c.slot();
+    if (c.lane < L)
+        slot[c.lane] = c.lane;
     wave_sync();
-    if (lane < 2 * L) {
-        const float my = lm[lane];
-        int rank = 0;
-        for (int e = 0; e < 2 * L; e++) {
-            const float o = lm[e];
-            rank += (o > my) || (o == my && e < lane);
-        }
-        if (rank < L)
-            sel[rank] = lane;
+    if (c.lg == 0) {
+        if (r0 < L)
+            slot[r0] = c.g;
+        if (r1 < L)
+            slot[r1] = c.g + L;
     }
     wave_sync();
+    const int sel = slot[c.g];
+    wave_sync();
+    return sel;
 }
 
 // ---------------------------------------------------------------------------
-// Alg. 2 on a non-root node RM(RN, MN).  Its LLRs are in abuf(MN); it writes
-// its L codewords to x, metrics to pm_out and ancestors to anc_out.
-// SPINE: the node is reached from the root by left steps only, so it is in
-// the permutation domain if it is an internal node.
+// Alg. 2 on a node RM(RN, MN) below the root; A holds this group's path LLRs.
+// SPINE: reached from the root by left steps only, so an internal node is in
+// the permutation domain.
 // ---------------------------------------------------------------------------
 template <int M, int R, int L, int MN, int RN, bool SPINE>
-__device__ void node(const Ws<M, R, L> &w, int pfht, const float *pm_in, uint8_t *x, float *pm_out, int *anc_out)
+__device__ __forceinline__ NodeRes<(1 << MN), kWave / L> node(const Ctx<M, R, L> &c,
+                                                               float (&A)[Lay<(1 << MN), kWave / L>::RR], float pm)
 {
     constexpr int n = 1 << MN;
-    constexpr int h = n / 2;
-    const int lane = lane_id();
+    constexpr int G = kWave / L;
+    using Ly = Lay<n, G>;
+    constexpr int RR = Ly::RR;
     if constexpr (1 < RN && RN < MN - 1) {
-        float *A = w.abuf(MN);
-        const bool is_per = SPINE && pfht;
-        int *sel = w.sel(MN);
-        const uint32_t *maps = w.maps();
-        constexpr int v = M - MN; // depth on the spine
-        constexpr int base = 2 * L + 4 * L * v;
-        if (is_per) {
-            perm_select<M, R, L, MN>(
-                w, maps + base * kMapWords,
-                [&](int l, uint32_t i) { return A[l * n + i]; }, sel);
-            float *T = w.ptmp();
-            for (int e = lane; e < L * n; e += kWave) {
-                const int l = e / n;
-                const uint32_t i = (uint32_t)(e % n);
-                const int c = sel[l];
-                T[e] = A[(c % L) * n + amap<MN>(maps + (base + c) * kMapWords, i)];
+        using Lc = Lay<n / 2, G>;
+        int sel = 0;
+        bool is_per = false;
+        constexpr int v = M - MN;
+        constexpr int mbase = 2 * L + 4 * L * v; // candidate maps of this spine node
+        float *stage = c.stage();
+        if constexpr (SPINE) {
+            if (c.pfht) {
+                is_per = true;
+                if (c.lg < Ly::ACT) {
+#pragma unroll
+                    for (int j = 0; j < RR; j++)
+                        stage[c.g * n + c.lg + G * j] = A[j];
+                }
+                wave_sync();
+                sel = perm_select<M, R, L, MN>(c, c.maps() + mbase * kMapWords,
+                                               [&](int path, uint32_t p) { return stage[path * n + p]; });
+                const int org = sel % L;
+                uint32_t pos[RR];
+                map_positions<MN, G, RR>(c.maps() + (mbase + sel) * kMapWords, c.lg, pos);
+#pragma unroll
+                for (int j = 0; j < RR; j++)
+                    A[j] = stage[org * n + pos[j]];
+                pm = from_lane(pm, org * G);
+                wave_sync();
             }
-            if (lane < L)
-                w.ppm(MN)[lane] = pm_in[sel[lane] % L];
-            wave_sync();
-            for (int e = lane; e < L * n; e += kWave)
-                A[e] = T[e];
-            pm_in = w.ppm(MN);
-            wave_sync();
         }
-        // left child on f
-        float *C = w.abuf(MN - 1);
-        for (int e = lane; e < L * h; e += kWave) {
-            const int l = e / h, i = e % h;
-            C[e] = f_minsum(A[l * n + i], A[l * n + i + h]);
-        }
-        wave_sync();
-        node<M, R, L, MN - 1, RN - 1, SPINE>(w, pfht, pm_in, w.xl(MN - 1), w.pmL(MN - 1), w.ancL(MN - 1));
-        // right child on g, reading the surviving ancestor's LLRs
-        const uint8_t *XL = w.xl(MN - 1);
-        const int *ancL = w.ancL(MN - 1);
-        for (int e = lane; e < L * h; e += kWave) {
-            const int l = e / h, i = e % h;
-            const int k = ancL[l];
-            C[e] = g_func(A[k * n + i], A[k * n + i + h], XL[e]);
-        }
-        wave_sync();
-        node<M, R, L, MN - 1, RN, false>(w, pfht, w.pmL(MN - 1), w.xr(MN - 1), w.pmR(MN - 1), w.ancR(MN - 1));
-        // combine (x_gamma ^ x_lambda, x_gamma)
-        const uint8_t *XR = w.xr(MN - 1);
-        const int *ancR = w.ancR(MN - 1);
-        uint8_t *XO = is_per ? w.xperm() : x;
-        for (int e = lane; e < L * h; e += kWave) {
-            const int l = e / h, i = e % h;
-            const int k = ancR[l];
-            const uint8_t xr = XR[e];
-            XO[l * n + i] = (uint8_t)(xr ^ XL[k * h + i]);
-            XO[l * n + i + h] = xr;
-        }
-        if (lane < L) {
-            const int a = ancL[ancR[lane]];
-            pm_out[lane] = w.pmR(MN - 1)[lane];
-            anc_out[lane] = is_per ? (sel[a] % L) : a;
-        }
-        wave_sync();
-        if (is_per) {
-            // undo the selected permutation: x[p(i)] = x'[i]  <=>  x[j] = x'[p^{-1}(j)]
-            for (int e = lane; e < L * n; e += kWave) {
-                const int l = e / n;
-                const uint32_t j = (uint32_t)(e % n);
-                const int a = ancL[ancR[l]];
-                const int c = sel[a];
-                x[e] = XO[l * n + amap<MN>(maps + (base + 2 * L + c) * kMapWords, j)];
+        float C[Lc::RR];
+        f_step<n, G>(A, C);
+        const auto rl = node<M, R, L, MN - 1, RN - 1, SPINE>(c, C, pm);
+        float Aa[RR];
+#pragma unroll
+        for (int j = 0; j < RR; j++)
+            Aa[j] = from_lane(A[j], rl.anc * G + c.lg);
+        g_step<n, G>(Aa, rl.x, C);
+        const auto rr = node<M, R, L, MN - 1, RN, false>(c, C, rl.pm);
+        const auto xl = (typename Lc::Mask)from_lane((uint64_t)rl.x, rr.anc * G + c.lg);
+        int anc = from_lane(rl.anc, rr.anc * G);
+        auto x = combine<n, G>(xl, rr.x, c.lg);
+        if constexpr (SPINE) {
+            if (is_per) {
+                // back to the node's input order: x[p(i)] = x'[i], read as x[j] = x'[p^{-1}(j)]
+                const int csel = from_lane(sel, anc * G);
+                uint8_t *sb = (uint8_t *)stage;
+                if (c.lg < Ly::ACT) {
+#pragma unroll
+                    for (int j = 0; j < RR; j++)
+                        sb[c.g * n + c.lg + G * j] = (uint8_t)((x >> j) & 1u);
+                }
+                wave_sync();
+                uint32_t pos[RR];
+                map_positions<MN, G, RR>(c.maps() + (mbase + 2 * L + csel) * kMapWords, c.lg, pos);
+                typename Ly::Mask y = 0;
+#pragma unroll
+                for (int j = 0; j < RR; j++)
+                    y |= (typename Ly::Mask)(sb[c.g * n + pos[j]] & 1u) << j;
+                x = c.lg < Ly::ACT ? y : (typename Ly::Mask)0;
+                anc = csel % L;
+                wave_sync();
             }
-            wave_sync();
         }
+        return {x, rr.pm, anc};
     } else if constexpr (RN == 1) {
-        fhtl_leaf<M, R, L, MN>(w, w.abuf(MN), pm_in, x, pm_out, anc_out);
-    } else if constexpr (RN == MN - 1) {
-        spcl_leaf<M, R, L, MN>(w, w.abuf(MN), pm_in, x, pm_out, anc_out);
+        return fhtl<M, R, L, MN>(c, A, pm);
+    } else {
+        static_assert(RN == MN - 1, "leaf must be RM(1,s) or RM(s-1,s)");
+        return spcl<M, R, L, MN>(c, A, pm);
     }
 }
 
+// Result of one decoder at the root for the path held by this group.
+template <int M, int R, int L>
+struct RootRes {
+    uint64_t xlo, xhi; // codeword masks (internal root: first and second half)
+    float pm;
+    int invmap; // index of the inverse map back to channel order
+};
+
 // ---------------------------------------------------------------------------
-// One decoder (Alg. 2 at the root, Alg. 5 loop body).  maps_g: this decoder's
-// maps in global memory.  Returns with pmroot/ancroot/xroot filled and
-// rmap[l] = forward map index of root path l.
+// Alg. 2 at the root of one decoder: the L paths start from the channel LLRs
+// through their initial maps; at an internal root in p-FHT mode the 2L
+// candidates are composed maps (initial map of path c mod L, then candidate c).
 // ---------------------------------------------------------------------------
 template <int M, int R, int L>
-__device__ void decode_root(const Ws<M, R, L> &w, int pfht)
+__device__ __forceinline__ RootRes<M, R, L> decode_root(const Ctx<M, R, L> &c)
 {
     using Sh = Shape<M, R, L>;
     constexpr int N = Sh::N;
-    constexpr int h = N / 2;
-    const int lane = lane_id();
-    const float *Y = w.y();
-    const uint32_t *maps = w.maps();
-    int *rmap = w.rmap();
-    float *zero = w.zero();
-    if (lane < L)
-        zero[lane] = 0.0f;
-
+    constexpr int G = Sh::G;
+    const float *Y = c.y();
+    const uint32_t *maps = c.maps();
     if constexpr (!Sh::ROOT_LEAF) {
-        const bool is_per = pfht != 0;
-        if (is_per) {
-            // candidate c: composite map (initial map of path c mod L, then candidate c)
-            perm_select<M, R, L, M>(
-                w, maps + 2 * L * kMapWords, [&](int, uint32_t i) { return Y[i]; }, w.sel(M));
-            if (lane < L)
-                rmap[lane] = 2 * L + w.sel(M)[lane];
-        } else {
-            if (lane < L)
-                rmap[lane] = lane;
+        constexpr int h = N / 2;
+        using Lc = Lay<h, G>;
+        constexpr int RC = Lc::RR;
+        int rmap = c.g;
+        if (c.pfht)
+            rmap = 2 * L + perm_select<M, R, L, M>(c, maps + 2 * L * kMapWords, [&](int, uint32_t p) { return Y[p]; });
+        float C[RC];
+        {
+            const uint32_t *mp = maps + rmap * kMapWords;
+            uint32_t pos[RC];
+            map_positions<M - 1, G, RC>(mp, c.lg, pos);
+            const uint32_t colh = mp[M - 1];
+#pragma unroll
+            for (int j = 0; j < RC; j++)
+                C[j] = f_minsum(Y[pos[j]], Y[pos[j] ^ colh]);
         }
-        wave_sync();
-        float *C = w.abuf(M - 1);
-        for (int e = lane; e < L * h; e += kWave) {
-            const int l = e / h, i = e % h;
-            const uint32_t *mp = maps + rmap[l] * kMapWords;
-            const uint32_t p = amap<M>(mp, (uint32_t)i);
-            C[e] = f_minsum(Y[p], Y[p ^ mp[M - 1]]);
+        const auto rl = node<M, R, L, M - 1, R - 1, true>(c, C, 0.0f);
+        {
+            const uint32_t *mp = maps + from_lane(rmap, rl.anc * G) * kMapWords;
+            uint32_t pos[RC];
+            map_positions<M - 1, G, RC>(mp, c.lg, pos);
+            const uint32_t colh = mp[M - 1];
+#pragma unroll
+            for (int j = 0; j < RC; j++)
+                C[j] = g_func(Y[pos[j]], Y[pos[j] ^ colh], (uint32_t)(rl.x >> j) & 1u);
         }
-        wave_sync();
-        node<M, R, L, M - 1, R - 1, true>(w, pfht, zero, w.xl(M - 1), w.pmL(M - 1), w.ancL(M - 1));
-        const uint8_t *XL = w.xl(M - 1);
-        const int *ancL = w.ancL(M - 1);
-        for (int e = lane; e < L * h; e += kWave) {
-            const int l = e / h, i = e % h;
-            const uint32_t *mp = maps + rmap[ancL[l]] * kMapWords;
-            const uint32_t p = amap<M>(mp, (uint32_t)i);
-            C[e] = g_func(Y[p], Y[p ^ mp[M - 1]], XL[e]);
-        }
-        wave_sync();
-        node<M, R, L, M - 1, R, false>(w, pfht, w.pmL(M - 1), w.xr(M - 1), w.pmR(M - 1), w.ancR(M - 1));
-        const uint8_t *XR = w.xr(M - 1);
-        const int *ancR = w.ancR(M - 1);
-        uint8_t *XO = w.xroot();
-        for (int e = lane; e < L * h; e += kWave) {
-            const int l = e / h, i = e % h;
-            const uint8_t xr = XR[e];
-            XO[l * N + i] = (uint8_t)(xr ^ XL[ancR[l] * h + i]);
-            XO[l * N + i + h] = xr;
-        }
-        if (lane < L) {
-            w.pmroot()[lane] = w.pmR(M - 1)[lane];
-            w.ancroot()[lane] = ancL[ancR[lane]];
-        }
-        wave_sync();
+        const auto rr = node<M, R, L, M - 1, R, false>(c, C, rl.pm);
+        const auto xl = (typename Lc::Mask)from_lane((uint64_t)rl.x, rr.anc * G + c.lg);
+        const int anc = from_lane(rl.anc, rr.anc * G);
+        const int inv = from_lane(rmap, anc * G) + (c.pfht ? 2 * L : L);
+        return {(uint64_t)(xl ^ rr.x), (uint64_t)rr.x, rr.pm, inv};
     } else {
-        // leaf root: the L paths start from y through their initial maps
-        if (lane < L)
-            rmap[lane] = lane;
-        wave_sync();
-        float *A = w.aroot();
-        for (int e = lane; e < L * N; e += kWave) {
-            const int l = e / N;
-            A[e] = Y[amap<M>(maps + l * kMapWords, (uint32_t)(e % N))];
+        using Ly = Lay<N, G>;
+        constexpr int RN = Ly::RR;
+        float A[RN];
+        {
+            uint32_t pos[RN];
+            map_positions<M, G, RN>(maps + c.g * kMapWords, c.lg, pos);
+#pragma unroll
+            for (int j = 0; j < RN; j++)
+                A[j] = Y[pos[j]];
         }
-        wave_sync();
+        NodeRes<N, G> res;
         if constexpr (R == 1)
-            fhtl_leaf<M, R, L, M>(w, A, zero, w.xroot(), w.pmroot(), w.ancroot());
+            res = fhtl<M, R, L, M>(c, A, 0.0f);
         else
-            spcl_leaf<M, R, L, M>(w, A, zero, w.xroot(), w.pmroot(), w.ancroot());
+            res = spcl<M, R, L, M>(c, A, 0.0f);
+        return {(uint64_t)res.x, 0ull, res.pm, L + res.anc};
     }
 }
 
@@ -715,67 +858,91 @@ __global__ void __launch_bounds__(256) rm_decode_kernel(KernelArgs args)
 {
     using Sh = Shape<M, R, L>;
     constexpr int N = Sh::N;
+    constexpr int G = Sh::G;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int wave = threadIdx.x / kWave;
-    const int lane = lane_id();
-    Ws<M, R, L> w(smem + wave * Sh::BYTES);
+    const int wave = (int)(threadIdx.x / kWave);
+    Ctx<M, R, L> c;
+    c.base = smem + wave * Sh::BYTES;
+    c.lane = lane_id();
+    c.g = c.lane / G;
+    c.lg = c.lane % G;
+    c.pfht = args.pfht;
     const int64_t stride = (int64_t)gridDim.x * args.waves;
     for (int64_t f = (int64_t)blockIdx.x * args.waves + wave; f < args.n_frames; f += stride) {
         const float *src = args.llr + f * N;
-        for (int i = lane; i < N; i += kWave)
-            w.y()[i] = src[i];
-        for (int i = lane; i < N; i += kWave)
-            w.xbest()[i] = 0;
-        if (lane == 0) {
-            w.bestpm()[0] = __builtin_inff();
-            w.bestmap()[0] = 0;
-        }
-        wave_sync();
+        for (int i = c.lane; i < N; i += kWave)
+            c.y()[i] = src[i];
+        float best = __builtin_inff();
+        int bestmap = 0;
+        uint64_t *xb = c.xbest();
+        if (c.lane < 2 * G)
+            xb[c.lane] = 0ull;
         for (int d = 0; d < args.P; d++) {
             const uint32_t *mg = args.maps + (size_t)d * args.maps_per_dec * kMapWords;
-            for (int i = lane; i < args.maps_per_dec * kMapWords; i += kWave)
-                w.maps()[i] = mg[i];
             wave_sync();
-            decode_root<M, R, L>(w, args.pfht);
+            for (int i = c.lane; i < args.maps_per_dec * kMapWords; i += kWave)
+                c.maps()[i] = mg[i];
+            wave_sync();
+            const RootRes<M, R, L> r = decode_root<M, R, L>(c);
             // Alg. 5: first minimum over the list, replace only if strictly smaller
-            const float *pmr = w.pmroot();
-            int ls = 0;
-            for (int l = 1; l < L; l++)
-                if (pmr[l] < pmr[ls])
-                    ls = l;
-            const float pbest = w.bestpm()[0];
-            if (pmr[ls] < pbest) {
-                const uint8_t *xs = w.xroot() + ls * N;
-                for (int i = lane; i < N; i += kWave)
-                    w.xbest()[i] = xs[i];
-                const int a = w.ancroot()[ls];
-                const int inv = w.rmap()[a] + (Sh::ROOT_LEAF || !args.pfht ? L : 2 * L);
-                wave_sync();
-                if (lane == 0) {
-                    w.bestpm()[0] = pmr[ls];
-                    w.bestmap()[0] = d * args.maps_per_dec + inv;
+            float pmin = from_lane(r.pm, 0);
+            int lstar = 0;
+#pragma unroll
+            for (int q = 1; q < L; q++) {
+                const float o = from_lane(r.pm, q * G);
+                if (o < pmin) {
+                    pmin = o;
+                    lstar = q;
                 }
             }
-            wave_sync();
-        }
-        // map the winner back to channel order and pack bits
-        const uint32_t *mi = args.maps + (size_t)w.bestmap()[0] * kMapWords;
-        uint8_t *ob = args.out_bits + f * (N / 8);
-        for (int j0 = 0; j0 < N; j0 += kWave) {
-            const int j = j0 + lane;
-            uint32_t bit = 0;
-            if (j < N)
-                bit = w.xbest()[amap<M>(mi, (uint32_t)j)];
-            const uint64_t mask = __ballot(bit != 0);
-            if (N >= kWave) {
-                if (lane == 0)
-                    *(uint64_t *)(ob + j0 / 8) = mask;
-            } else if (lane < N / 8) {
-                ob[lane] = (uint8_t)(mask >> (8 * lane));
+            if (pmin < best) {
+                best = pmin;
+                bestmap = d * args.maps_per_dec + from_lane(r.invmap, lstar * G);
+                if (c.g == lstar) {
+                    xb[c.lg] = r.xlo;
+                    xb[G + c.lg] = r.xhi;
+                }
             }
         }
-        if (args.out_pm && lane == 0)
-            args.out_pm[f] = w.bestpm()[0];
+        wave_sync();
+        // the winner back in channel order, packed
+        const uint32_t *mi = args.maps + (size_t)bestmap * kMapWords;
+        uint32_t col[M + 1];
+#pragma unroll
+        for (int k = 0; k < M; k++)
+            col[k] = mi[k];
+        col[M] = mi[kMapB];
+        uint8_t *ob = args.out_bits + f * (N / 8);
+#pragma unroll
+        for (int j0 = 0; j0 < N; j0 += kWave) {
+            const uint32_t j = (uint32_t)(j0 + c.lane);
+            uint32_t e = col[M];
+#pragma unroll
+            for (int k = 0; k < M; k++)
+                e ^= ((j >> k) & 1u) ? col[k] : 0u;
+            uint32_t bit = 0;
+            if (j < (uint32_t)N) {
+                e &= (uint32_t)(N - 1);
+                if constexpr (!Sh::ROOT_LEAF) {
+                    constexpr uint32_t h = N / 2;
+                    const uint32_t ee = e < h ? e : e - h;
+                    const uint64_t w = xb[(e < h ? 0 : G) + (ee % G)];
+                    bit = (uint32_t)(w >> (ee / G)) & 1u;
+                } else {
+                    bit = (uint32_t)(xb[e % G] >> (e / G)) & 1u;
+                }
+            }
+            const uint64_t mask = __ballot(bit != 0);
+            if constexpr (N >= kWave) {
+                if (c.lane == 0)
+                    *(uint64_t *)(ob + j0 / 8) = mask;
+            } else {
+                if (c.lane < N / 8)
+                    ob[c.lane] = (uint8_t)(mask >> (8 * c.lane));
+            }
+        }
+        if (args.out_pm && c.lane == 0)
+            args.out_pm[f] = best;
         wave_sync();
     }
 }

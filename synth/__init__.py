@@ -16,6 +16,8 @@ Frames are generated in fixed chunks of ``CHUNK`` frames, chunk c seeded by
 from __future__ import annotations
 
 import itertools
+import os
+from concurrent.futures import ThreadPoolExecutor
 from math import comb
 
 import numpy as np
@@ -50,7 +52,8 @@ def _chunk(m, r, seed, c, ebn0_db_chunk, mon):
     n = 1 << m
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), int(c)])))
     coef = rng.integers(0, 2, size=(CHUNK, mon.shape[0]), dtype=np.uint8)
-    x = ((coef.astype(np.int32) @ mon.astype(np.int32)) & 1).astype(np.uint8)
+    # integer sums of at most K ones are exact in binary32
+    x = ((coef.astype(np.float32) @ mon.astype(np.float32)).astype(np.int32) & 1).astype(np.uint8)
     noise = rng.standard_normal((CHUNK, n))
     s2 = np.broadcast_to(sigma2(ebn0_db_chunk, m, r), (CHUNK,)).reshape(CHUNK, 1)
     y = (1.0 - 2.0 * x) + np.sqrt(s2) * noise
@@ -71,7 +74,8 @@ def frames(m: int, r: int, n_frames: int, ebn0_db, seed: int = 0):
         assert ebn0_db.shape == (n_frames,)
     xs = np.empty((n_frames, n), dtype=np.uint8)
     ls = np.empty((n_frames, n), dtype=np.float32)
-    for c in range((n_frames + CHUNK - 1) // CHUNK):
+
+    def one(c):
         f0 = c * CHUNK
         f1 = min(n_frames, f0 + CHUNK)
         if per_frame:
@@ -83,6 +87,10 @@ def frames(m: int, r: int, n_frames: int, ebn0_db, seed: int = 0):
         x, llr = _chunk(m, r, seed, c, e, mon)
         xs[f0:f1] = x[: f1 - f0]
         ls[f0:f1] = llr[: f1 - f0]
+
+    n_chunks = (n_frames + CHUNK - 1) // CHUNK
+    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1, max(1, n_chunks))) as ex:
+        list(ex.map(one, range(n_chunks)))
     return xs, ls
 
 
