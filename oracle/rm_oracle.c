@@ -12,6 +12,15 @@
  * arg-max, hard decisions) is taken on the same values as a GPU path that
  * follows the same operation order.  Where the paper leaves an order or a tie
  * open, the choice made here is stated in a comment and listed as a reading.
+ *
+ * Pins (tests/test_oracle_pins.py): code tables against printed values; FHT
+ * and SPC decoding against brute force; the decoder against exact
+ * invariants (codeword membership, final metric = correlation metric,
+ * noiseless input, sign-flip equivariance, ML at r = 1 roots, Wagner at
+ * r = m-1 roots, exhaustive ML on RM(2,5)); FER against Fig. 5(a).
+ * Parity unpinned: tie-break order among equal values and the permutation
+ * draw (fixed by contract; the draw is checked only for being an
+ * automorphism and against the library's independent implementation).
  */
 #include "rm_oracle.h"
 
