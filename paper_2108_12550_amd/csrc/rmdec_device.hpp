@@ -63,7 +63,8 @@ __device__ __forceinline__ void wave_sync()
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp(uint32_t v)
 {
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+    // all patterns used read lanes of the same row, so the bound control never applies
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, true);
 }
 
 // max/min of two doubles known to be ordinary (non-NaN) numbers; written as
@@ -99,6 +100,35 @@ __device__ __forceinline__ uint32_t xor_lanes_u32(uint32_t v)
         return (uint32_t)__builtin_amdgcn_ds_bpermute((lane_id() ^ W) << 2, (int)v);
 }
 
+// value held by lane (lane ^ W) for any W < 64: the bits of W below 8 are
+// one or two DPP moves (row_half_mirror is lane ^ 7 within 8 lanes)
+template <int Q>
+__device__ __forceinline__ uint32_t xor_quad(uint32_t v)
+{
+    if constexpr (Q == 0)
+        return v;
+    else if constexpr (Q == 1)
+        return dpp<0xB1>(v);
+    else if constexpr (Q == 2)
+        return dpp<0x4E>(v);
+    else
+        return dpp<0x1B>(v);
+}
+template <int W>
+__device__ __forceinline__ uint32_t xor_any(uint32_t v)
+{
+    if constexpr (W >= 32)
+        return xor_any<W - 32>(xor_lanes_u32<32>(v));
+    else if constexpr (W >= 16)
+        return xor_any<W - 16>(xor_lanes_u32<16>(v));
+    else if constexpr (W >= 8)
+        return xor_any<W - 8>(xor_lanes_u32<8>(v));
+    else if constexpr (W >= 4)
+        return xor_quad<W ^ 7>(dpp<0x141>(v));
+    else
+        return xor_quad<W>(v);
+}
+
 template <int W>
 __device__ __forceinline__ float xor_lanes(float v)
 {
@@ -117,6 +147,20 @@ template <int W>
 __device__ __forceinline__ double xor_lanes(double v)
 {
     return __longlong_as_double((long long)xor_lanes<W>((uint64_t)__double_as_longlong(v)));
+}
+
+// The wave's LDS is addressed by byte offset from the start of the dynamic
+// shared segment.
+extern __shared__ __align__(16) unsigned char rm_smem[];
+__device__ __forceinline__ float lds_f32(uint32_t byte_addr) { return *(const float *)(rm_smem + byte_addr); }
+__device__ __forceinline__ uint32_t lds_u32(uint32_t byte_addr) { return *(const uint32_t *)(rm_smem + byte_addr); }
+
+// min(|a|, |b|) for ordinary numbers, one instruction
+__device__ __forceinline__ float min_abs(float a, float b)
+{
+    float r;
+    asm("v_min_f32_e64 %0, |%1|, |%2|" : "=v"(r) : "v"(a), "v"(b));
+    return r;
 }
 
 // value held by lane `src`
@@ -220,49 +264,62 @@ struct Lay {
     static constexpr Mask FULL = RR >= 64 ? ~(Mask)0 : (Mask)(((uint64_t)1 << RR) - 1);
 };
 
-template <int M, int R, int L>
+template <int M, int R, int L, int D>
 struct Shape {
     static constexpr int N = 1 << M;
-    static constexpr int G = kWave / L;
+    static constexpr int G = kWave / (L * D); // lanes per path; D decoders of L paths per wave
     static constexpr int LG = ilog2(G);
     static constexpr int NPERM = perm_spine(M, R);
     static constexpr bool ROOT_LEAF = !(1 < R && R < M - 1);
     static constexpr int TAU = max_spc_tau(M, R, L);
     static constexpr int MAPS_PER_DEC = 2 * L + 4 * L * NPERM;
 
-    // byte offsets of the per-wave LDS slice
+    // byte offsets of the per-wave LDS slice; per-decoder arrays are [D][...]
     static constexpr int O_Y = 0;
     static constexpr int O_MAPS = align16(O_Y + 4 * N);
-    static constexpr int O_STAGE = align16(O_MAPS + 4 * kMapWords * MAPS_PER_DEC); // spine nodes below the root
-    static constexpr int STAGE_BYTES = NPERM >= 2 ? 4 * L * N / 2 : 0;
+    // y at the slice start and the staging area aligned to 4N bytes (slices are
+    // a multiple of 4N) so that byte addresses of map images can be formed by XOR
+    static constexpr int O_STAGE = ((O_MAPS + 4 * kMapWords * MAPS_PER_DEC * D + 4 * N - 1) / (4 * N)) * (4 * N);
+    static constexpr int STAGE_BYTES = NPERM >= 2 ? 4 * D * L * N / 2 : 0;
     static constexpr int O_CPM = align16(O_STAGE + STAGE_BYTES); // list merges: metrics
-    static constexpr int O_CINF = O_CPM + 4 * L * L;              // list merges: payload
-    static constexpr int O_CAUX = O_CINF + 4 * L * L;             // list merges: payload 2
-    static constexpr int O_SLOT = O_CAUX + 4 * L * L;             // survivors
-    static constexpr int O_SPCA = O_SLOT + 4 * L;                 // SPC: |alpha| at o_t [L][TAU+1]
-    static constexpr int O_SPCI = O_SPCA + 4 * L * (TAU + 1);     // SPC: o_t [L][TAU+1]
-    static constexpr int O_SPCP = O_SPCI + 4 * L * (TAU + 1);     // SPC: parity | hd(o_0) << 1
-    static constexpr int O_XBEST = align16(O_SPCP + 4 * L);       // winner's codeword masks, 2G words
-    static constexpr int BYTES = align16(O_XBEST + 16 * G);
+    static constexpr int O_CINF = O_CPM + 4 * D * L * L;          // list merges: payload
+    static constexpr int O_CAUX = O_CINF + 4 * D * L * L;         // list merges: payload 2
+    static constexpr int O_SLOT = O_CAUX + 4 * D * L * L;         // survivors
+    static constexpr int O_SPCA = O_SLOT + 4 * D * L;             // SPC: |alpha| at o_t [D*L][TAU+1]
+    static constexpr int O_SPCI = O_SPCA + 4 * D * L * (TAU + 1); // SPC: o_t [D*L][TAU+1]
+    static constexpr int O_SPCP = O_SPCI + 4 * D * L * (TAU + 1); // SPC: parity | hd(o_0) << 1
+    static constexpr int O_XBEST = align16(O_SPCP + 4 * D * L);   // winner's codeword masks, 2G words
+    static constexpr int BYTES = ((O_XBEST + 16 * G + 4 * N - 1) / (4 * N)) * (4 * N);
 };
 
-// Per-wave context.
-template <int M, int R, int L>
+// Per-wave context.  Lane = (decoder ds, path g, lane-in-group lg); the
+// decoder's paths occupy groups gb .. gb+L-1 of the wave.
+template <int M, int R, int L, int D>
 struct Ctx {
-    using S = Shape<M, R, L>;
+    using S = Shape<M, R, L, D>;
     unsigned char *base;
-    int lane, g, lg;
+    int lane, lg;
+    int g;  // path within the decoder
+    int gb; // first group of this lane's decoder
+    int ds; // decoder within the wave
     int pfht;
+    __device__ int lane_of(int path) const { return (gb + path) * S::G + lg; } // same element, other path
+    __device__ int lead_of(int path) const { return (gb + path) * S::G; }      // first lane of a path
     __device__ float *y() const { return (float *)(base + S::O_Y); }
-    __device__ uint32_t *maps() const { return (uint32_t *)(base + S::O_MAPS); }
+    __device__ uint32_t y_addr() const { return (uint32_t)(base - rm_smem) + S::O_Y; }
+    __device__ uint32_t stage_addr() const { return (uint32_t)(base - rm_smem) + S::O_STAGE; }
+    __device__ uint32_t *maps_all() const { return (uint32_t *)(base + S::O_MAPS); }
+    __device__ uint32_t *maps() const { return maps_all() + ds * S::MAPS_PER_DEC * kMapWords; }
     __device__ float *stage() const { return (float *)(base + S::O_STAGE); }
-    __device__ float *cpm() const { return (float *)(base + S::O_CPM); }
-    __device__ uint32_t *cinf() const { return (uint32_t *)(base + S::O_CINF); }
-    __device__ uint32_t *caux() const { return (uint32_t *)(base + S::O_CAUX); }
-    __device__ int *slot() const { return (int *)(base + S::O_SLOT); }
-    __device__ float *spca() const { return (float *)(base + S::O_SPCA); }
-    __device__ int *spci() const { return (int *)(base + S::O_SPCI); }
-    __device__ uint32_t *spcp() const { return (uint32_t *)(base + S::O_SPCP); }
+    __device__ float *cpm_all() const { return (float *)(base + S::O_CPM); }
+    __device__ float *cpm() const { return cpm_all() + ds * L * L; }
+    __device__ uint32_t *cinf() const { return (uint32_t *)(base + S::O_CINF) + ds * L * L; }
+    __device__ uint32_t *caux() const { return (uint32_t *)(base + S::O_CAUX) + ds * L * L; }
+    __device__ int *slot_all() const { return (int *)(base + S::O_SLOT); }
+    __device__ int *slot() const { return slot_all() + ds * L; }
+    __device__ float *spca() const { return (float *)(base + S::O_SPCA) + ds * L * (S::TAU + 1); }
+    __device__ int *spci() const { return (int *)(base + S::O_SPCI) + ds * L * (S::TAU + 1); }
+    __device__ uint32_t *spcp() const { return (uint32_t *)(base + S::O_SPCP) + ds * L; }
     __device__ uint64_t *xbest() const { return (uint64_t *)(base + S::O_XBEST); }
 };
 
@@ -273,36 +330,43 @@ struct NodeRes {
     int anc;                    // input path it descends from
 };
 
-// Rank-based stable selection of the `keep` smallest of `cnt` metrics in
-// LDS (ties to the lower position): slot[r] receives the position of rank r.
-// slot[0..keep) must already hold valid positions.
-template <int cnt, int keep>
+// Rank-based stable selection, for each of the D decoders of the wave, of
+// the `keep` smallest of its `cnt` metrics in LDS (ties to the lower
+// position): slot[t*keep + r] receives
+// the position of its rank r (decoder t's metrics start at pm[t*STRIDE]).
+// Those slots must already hold valid positions.
+template <int cnt, int keep, int D, int STRIDE>
 __device__ __forceinline__ void select_smallest(const float *pm, int *slot, int lane)
 {
-    if (lane < cnt) {
-        const float my = pm[lane];
+    if (lane < cnt * D) {
+        const int seg = lane / cnt;
+        const int me = lane - seg * cnt;
+        const float *sp = pm + seg * STRIDE;
+        const float my = sp[me];
         int rank = 0;
 #pragma unroll
         for (int q = 0; q < cnt; q++) {
-            const float o = pm[q];
-            rank += (o < my) || (o == my && q < lane);
+            const float o = sp[q];
+            rank += (o < my) || (o == my && q < me);
         }
         if (rank < keep)
-            slot[rank] = lane;
+            slot[seg * keep + rank] = me;
     }
 }
 
-// Positions p(i) of elements i = lg + G j (j < RR) under an affine map on
-// F2^MD stored as columns: the lane part first, then one XOR per register.
+// Byte addresses of elements p(i), i = lg + G j (j < RR), of a vector at
+// byte address `base` (aligned to the vector's size, so XOR acts as
+// addition), under an affine map on F2^MD stored in LDS as byte-scaled
+// columns and offset: the lane part first, then one XOR per register.
 template <int MD, int G, int RR>
-__device__ __forceinline__ void map_positions(const uint32_t *mp, int lg, uint32_t (&pos)[RR])
+__device__ __forceinline__ void map_positions(const uint32_t *mp, int lg, uint32_t base, uint32_t (&pos)[RR])
 {
     constexpr int LG = ilog2(G);
-    uint32_t base = mp[kMapB];
+    uint32_t b = base ^ mp[kMapB];
 #pragma unroll
     for (int k = 0; k < LG && k < MD; k++)
-        base ^= ((lg >> k) & 1) ? mp[k] : 0u;
-    pos[0] = base;
+        b ^= ((lg >> k) & 1) ? mp[k] : 0u;
+    pos[0] = b;
 #pragma unroll
     for (int j = 1; j < RR; j++)
         pos[j] = pos[j & (j - 1)] ^ mp[LG + __builtin_ctz(j)];
@@ -375,12 +439,12 @@ __device__ __forceinline__ double fht_key(float f, uint32_t i)
 // FHTL leaf RM(1,s): Alg. 3 over Alg. 4 with the metric of Eq. (10).
 // A: this group's path LLRs (row layout), pm: its metric.
 // ---------------------------------------------------------------------------
-template <int M, int R, int L, int S>
-__device__ __forceinline__ NodeRes<(1 << S), kWave / L> fhtl(const Ctx<M, R, L> &c,
-                                                              float (&A)[Lay<(1 << S), kWave / L>::RR], float pm)
+template <int M, int R, int L, int D, int S>
+__device__ __forceinline__ NodeRes<(1 << S), kWave / (L * D)> fhtl(const Ctx<M, R, L, D> &c,
+                                                              float (&A)[Lay<(1 << S), kWave / (L * D)>::RR], float pm)
 {
     constexpr int n = 1 << S;
-    constexpr int G = kWave / L;
+    constexpr int G = kWave / (L * D);
     using Ly = Lay<n, G>;
     constexpr int RR = Ly::RR;
     constexpr int ACT = Ly::ACT;
@@ -397,16 +461,18 @@ __device__ __forceinline__ NodeRes<(1 << S), kWave / L> fhtl(const Ctx<M, R, L> 
 
     fht_stages<n / 2, G, RR>(A, lg);
 
-    // lane-local two largest keys
-    double b1 = 0.0, b2 = 0.0;
+    // lane-local three largest keys
+    double b1 = 0.0, b2 = 0.0, b3 = 0.0;
 #pragma unroll
     for (int j = 0; j < RR; j++) {
         const double k = valid ? fht_key(A[j], (uint32_t)(lg + G * j)) : 0.0;
-        const double lo = dmin(b1, k);
+        const double x1 = dmin(b1, k);
         b1 = dmax(b1, k);
-        b2 = dmax(b2, lo);
+        const double x2 = dmin(b2, x1);
+        b2 = dmax(b2, x1);
+        b3 = dmax(b3, x2);
     }
-    bool b2ok = true;
+    int left = 3; // keys of this lane known to be its largest below the last pop
 
     // K rounds: the group's largest remaining key is the next candidate
     float mypm = 0.0f;
@@ -423,28 +489,32 @@ __device__ __forceinline__ NodeRes<(1 << S), kWave / L> fhtl(const Ctx<M, R, L> 
         }
         if (t + 1 < K) {
             const bool own = valid && (b1 == w);
-            const bool need = own && !b2ok;
+            if (own) {
+                b1 = b2;
+                b2 = b3;
+                b3 = 0.0;
+                left--;
+            }
+            const bool need = own && left == 0;
             if (__any(need)) {
-                // the owner's second key was already used: rescan below w
-                double nb1 = 0.0, nb2 = 0.0;
+                // the owner used up its known keys: rescan below w
+                double n1 = 0.0, n2 = 0.0, n3 = 0.0;
 #pragma unroll
                 for (int j = 0; j < RR; j++) {
                     double k = valid ? fht_key(A[j], (uint32_t)(lg + G * j)) : 0.0;
                     k = k < w ? k : 0.0;
-                    const double lo = dmin(nb1, k);
-                    nb1 = dmax(nb1, k);
-                    nb2 = dmax(nb2, lo);
+                    const double x1 = dmin(n1, k);
+                    n1 = dmax(n1, k);
+                    const double x2 = dmin(n2, x1);
+                    n2 = dmax(n2, x1);
+                    n3 = dmax(n3, x2);
                 }
                 if (need) {
-                    b1 = nb1;
-                    b2 = nb2;
-                    b2ok = true;
+                    b1 = n1;
+                    b2 = n2;
+                    b3 = n3;
+                    left = 3;
                 }
-            }
-            if (own && !need) {
-                b1 = b2;
-                b2 = 0.0;
-                b2ok = false;
             }
         }
     }
@@ -457,10 +527,11 @@ __device__ __forceinline__ NodeRes<(1 << S), kWave / L> fhtl(const Ctx<M, R, L> 
         cpm[c.g * K + lg] = mypm;
         cinf[c.g * K + lg] = myinf;
     }
-    if (c.lane < L)
-        slot[c.lane] = c.lane;
+    if (c.lane < L * D)
+        c.slot_all()[c.lane] = c.lane % L;
     wave_sync();
-    select_smallest<L * K, L>(cpm, slot, c.lane);
+    static_assert(K == L, "list merge assumes min(L, 2^s) = L");
+    select_smallest<L * K, L, D, L * L>(c.cpm_all(), c.slot_all(), c.lane);
     wave_sync();
     const int e = slot[c.g];
     const float opm = cpm[e];
@@ -480,20 +551,32 @@ __device__ __forceinline__ NodeRes<(1 << S), kWave / L> fhtl(const Ctx<M, R, L> 
     return {x, opm, e / K};
 }
 
+// rank of this lane's value among the n values of its group (smaller first,
+// ties to the lower element index); partner element lg ^ w sits in lane ^ w
+template <int W, int n>
+__device__ __forceinline__ void spc_rank(uint32_t me, int lg, int &rank)
+{
+    if constexpr (W < n) {
+        const uint32_t o = xor_any<W>(me);
+        rank += (o < me) || (o == me && (lg ^ W) < lg);
+        spc_rank<W + 1, n>(me, lg, rank);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // SPCL leaf RM(s-1,s): Eqs. (2)-(6), tau = min(L, 2^s - 1) splits (0 if L = 1)
 // ---------------------------------------------------------------------------
-template <int M, int R, int L, int S>
-__device__ __forceinline__ NodeRes<(1 << S), kWave / L> spcl(const Ctx<M, R, L> &c,
-                                                              float (&A)[Lay<(1 << S), kWave / L>::RR], float pm)
+template <int M, int R, int L, int D, int S>
+__device__ __forceinline__ NodeRes<(1 << S), kWave / (L * D)> spcl(const Ctx<M, R, L, D> &c,
+                                                              float (&A)[Lay<(1 << S), kWave / (L * D)>::RR], float pm)
 {
     constexpr int n = 1 << S;
-    constexpr int G = kWave / L;
+    constexpr int G = kWave / (L * D);
     using Ly = Lay<n, G>;
     constexpr int RR = Ly::RR;
     constexpr int ACT = Ly::ACT;
     constexpr int tau = spc_tau(L, n);
-    constexpr int TS = Shape<M, R, L>::TAU + 1;
+    constexpr int TS = Shape<M, R, L, D>::TAU + 1;
     using MaskT = typename Ly::Mask;
     const int lg = c.lg;
     const int g = c.g;
@@ -507,14 +590,24 @@ __device__ __forceinline__ NodeRes<(1 << S), kWave / L> spcl(const Ctx<M, R, L> 
     const uint32_t par = bfly_xor<ACT / 2>((uint32_t)(__popcll((uint64_t)hd) & 1));
 
     // o_0 .. o_tau: |alpha| ascending, ties to the lower index
+    float *spca = c.spca();
+    int *spci = c.spci();
+    if constexpr (n <= G) {
+        // one element per lane: its rank among the node's n elements
+        const uint32_t me = __float_as_uint(fabsf(A[0]));
+        int rank = 0;
+        spc_rank<1, n>(me, lg, rank);
+        if (valid && rank <= tau) {
+            spca[g * TS + rank] = __uint_as_float(me);
+            spci[g * TS + rank] = lg;
+        }
+    } else {
     uint64_t key[RR];
 #pragma unroll
     for (int j = 0; j < RR; j++) {
         const uint32_t i = (uint32_t)(lg + G * j);
         key[j] = valid ? (((uint64_t)(0x7FFFFFFFu - __float_as_uint(fabsf(A[j]))) << 32) | (1024u - i)) : 0ull;
     }
-    float *spca = c.spca();
-    int *spci = c.spci();
 #pragma unroll
     for (int t = 0; t <= tau; t++) {
         uint64_t b = key[0];
@@ -530,11 +623,12 @@ __device__ __forceinline__ NodeRes<(1 << S), kWave / L> spcl(const Ctx<M, R, L> 
             spci[g * TS + t] = (int)(1024u - (uint32_t)w);
         }
     }
+    }
     uint32_t *spcp = c.spcp();
     wave_sync();
     const int o0 = spci[g * TS];
     const float a0 = spca[g * TS];
-    const uint32_t hd_o0 = (uint32_t)(from_lane((uint64_t)hd, g * G + (o0 % G)) >> (o0 / G)) & 1u;
+    const uint32_t hd_o0 = (uint32_t)(from_lane((uint64_t)hd, c.lead_of(g) + (o0 % G)) >> (o0 / G)) & 1u;
     if (lg == 0)
         spcp[g] = par | (hd_o0 << 1);
     float cur = pm;
@@ -562,10 +656,10 @@ __device__ __forceinline__ NodeRes<(1 << S), kWave / L> spcl(const Ctx<M, R, L> 
             cinf[e] = (uint32_t)src | ((lg ? (p ^ 1u) : p) << 8);
             caux[e] = lg ? (flips | (1u << t)) : flips;
         }
-        if (c.lane < L)
-            slot[c.lane] = c.lane;
+        if (c.lane < L * D)
+            c.slot_all()[c.lane] = c.lane % L;
         wave_sync();
-        select_smallest<2 * L, L>(cpm, slot, c.lane);
+        select_smallest<2 * L, L, D, L * L>(c.cpm_all(), c.slot_all(), c.lane);
         wave_sync();
         const int e = slot[g];
         cur = cpm[e];
@@ -577,7 +671,7 @@ __device__ __forceinline__ NodeRes<(1 << S), kWave / L> spcl(const Ctx<M, R, L> 
 
     // codeword: hard decisions of the source path, the taken flips, then the
     // parity of o_0 (Eq. (6))
-    MaskT x = (MaskT)from_lane((uint64_t)hd, src * G + lg);
+    MaskT x = (MaskT)from_lane((uint64_t)hd, c.lane_of(src));
     const uint32_t sp = spcp[src];
     const int so0 = spci[src * TS];
     const uint32_t fix = (sp & 1u) ^ (__popc(flips) & 1u) ^ ((sp >> 1) & 1u);
@@ -641,15 +735,16 @@ __device__ __forceinline__ typename Lay<n, G>::Mask combine(typename Lay<n / 2, 
 // ---------------------------------------------------------------------------
 // Permutation-domain selection at a node of size 2^MD (Alg. 2): candidate c
 // reads path c mod L through map c; LM_c = sum_i |f| over the halving tree;
-// the L largest survive (ties to the lower c).  src(path, position) reads the
-// node LLRs.  Returns the candidate that becomes this group's path.
+// the L largest survive (ties to the lower c).  src(path) is the LDS byte
+// address of that path's node LLRs.  Returns the candidate that becomes this
+// group's path.
 // ---------------------------------------------------------------------------
-template <int M, int R, int L, int MD, class Src>
-__device__ __forceinline__ int perm_select(const Ctx<M, R, L> &c, const uint32_t *cand_maps, Src src)
+template <int M, int R, int L, int D, int MD, class Src>
+__device__ __forceinline__ int perm_select(const Ctx<M, R, L, D> &c, const uint32_t *cand_maps, Src src)
 {
     constexpr int n = 1 << MD;
     constexpr int h = n / 2;
-    constexpr int G = kWave / L;
+    constexpr int G = kWave / (L * D);
     using Lh = Lay<h, G>;
     constexpr int RR = Lh::RR;
     const bool valid = c.lg < Lh::ACT;
@@ -658,28 +753,28 @@ __device__ __forceinline__ int perm_select(const Ctx<M, R, L> &c, const uint32_t
     for (int pass = 0; pass < 2; pass++) {
         const uint32_t *mp = cand_maps + (c.g + L * pass) * kMapWords;
         uint32_t pos[RR];
-        map_positions<MD - 1, G, RR>(mp, c.lg, pos);
+        map_positions<MD - 1, G, RR>(mp, c.lg, src(c.g), pos);
         const uint32_t colh = mp[MD - 1];
         float v[RR];
 #pragma unroll
         for (int j = 0; j < RR; j++)
-            v[j] = valid ? fminf(fabsf(src(c.g, pos[j])), fabsf(src(c.g, pos[j] ^ colh))) : 0.0f;
+            v[j] = valid ? min_abs(lds_f32(pos[j]), lds_f32(pos[j] ^ colh)) : 0.0f;
         lm[pass] = tree_sum<h, G, RR>(v);
     }
     // rank of candidates g and g+L among all 2L (larger LM first, ties to lower index)
     int r0 = 0, r1 = 0;
 #pragma unroll
     for (int q = 0; q < L; q++) {
-        const float o0 = from_lane(lm[0], q * G);
-        const float o1 = from_lane(lm[1], q * G);
+        const float o0 = from_lane(lm[0], c.lead_of(q));
+        const float o1 = from_lane(lm[1], c.lead_of(q));
         r0 += (o0 > lm[0]) || (o0 == lm[0] && q < c.g);
         r0 += (o1 > lm[0]);
         r1 += (o0 > lm[1]) || (o0 == lm[1]);
         r1 += (o1 > lm[1]) || (o1 == lm[1] && q < c.g);
     }
     int *slot = c.slot();
-    if (c.lane < L)
-        slot[c.lane] = c.lane;
+    if (c.lane < L * D)
+        c.slot_all()[c.lane] = c.lane % L;
     wave_sync();
     if (c.lg == 0) {
         if (r0 < L)
@@ -698,12 +793,12 @@ __device__ __forceinline__ int perm_select(const Ctx<M, R, L> &c, const uint32_t
 // SPINE: reached from the root by left steps only, so an internal node is in
 // the permutation domain.
 // ---------------------------------------------------------------------------
-template <int M, int R, int L, int MN, int RN, bool SPINE>
-__device__ __forceinline__ NodeRes<(1 << MN), kWave / L> node(const Ctx<M, R, L> &c,
-                                                               float (&A)[Lay<(1 << MN), kWave / L>::RR], float pm)
+template <int M, int R, int L, int D, int MN, int RN, bool SPINE>
+__device__ __forceinline__ NodeRes<(1 << MN), kWave / (L * D)> node(const Ctx<M, R, L, D> &c,
+                                                               float (&A)[Lay<(1 << MN), kWave / (L * D)>::RR], float pm)
 {
     constexpr int n = 1 << MN;
-    constexpr int G = kWave / L;
+    constexpr int G = kWave / (L * D);
     using Ly = Lay<n, G>;
     constexpr int RR = Ly::RR;
     if constexpr (1 < RN && RN < MN - 1) {
@@ -719,50 +814,52 @@ __device__ __forceinline__ NodeRes<(1 << MN), kWave / L> node(const Ctx<M, R, L>
                 if (c.lg < Ly::ACT) {
 #pragma unroll
                     for (int j = 0; j < RR; j++)
-                        stage[c.g * n + c.lg + G * j] = A[j];
+                        stage[(c.gb + c.g) * n + c.lg + G * j] = A[j];
                 }
                 wave_sync();
-                sel = perm_select<M, R, L, MN>(c, c.maps() + mbase * kMapWords,
-                                               [&](int path, uint32_t p) { return stage[path * n + p]; });
+                sel = perm_select<M, R, L, D, MN>(c, c.maps() + mbase * kMapWords,
+                                                  [&](int path) { return c.stage_addr() + (uint32_t)((c.gb + path) * n * 4); });
                 const int org = sel % L;
                 uint32_t pos[RR];
-                map_positions<MN, G, RR>(c.maps() + (mbase + sel) * kMapWords, c.lg, pos);
+                map_positions<MN, G, RR>(c.maps() + (mbase + sel) * kMapWords, c.lg,
+                                         c.stage_addr() + (uint32_t)((c.gb + org) * n * 4), pos);
 #pragma unroll
                 for (int j = 0; j < RR; j++)
-                    A[j] = stage[org * n + pos[j]];
-                pm = from_lane(pm, org * G);
+                    A[j] = lds_f32(pos[j]);
+                pm = from_lane(pm, c.lead_of(org));
                 wave_sync();
             }
         }
         float C[Lc::RR];
         f_step<n, G>(A, C);
-        const auto rl = node<M, R, L, MN - 1, RN - 1, SPINE>(c, C, pm);
+        const auto rl = node<M, R, L, D, MN - 1, RN - 1, SPINE>(c, C, pm);
         float Aa[RR];
 #pragma unroll
         for (int j = 0; j < RR; j++)
-            Aa[j] = from_lane(A[j], rl.anc * G + c.lg);
+            Aa[j] = from_lane(A[j], c.lane_of(rl.anc));
         g_step<n, G>(Aa, rl.x, C);
-        const auto rr = node<M, R, L, MN - 1, RN, false>(c, C, rl.pm);
-        const auto xl = (typename Lc::Mask)from_lane((uint64_t)rl.x, rr.anc * G + c.lg);
-        int anc = from_lane(rl.anc, rr.anc * G);
+        const auto rr = node<M, R, L, D, MN - 1, RN, false>(c, C, rl.pm);
+        const auto xl = (typename Lc::Mask)from_lane((uint64_t)rl.x, c.lane_of(rr.anc));
+        int anc = from_lane(rl.anc, c.lead_of(rr.anc));
         auto x = combine<n, G>(xl, rr.x, c.lg);
         if constexpr (SPINE) {
             if (is_per) {
                 // back to the node's input order: x[p(i)] = x'[i], read as x[j] = x'[p^{-1}(j)]
-                const int csel = from_lane(sel, anc * G);
-                uint8_t *sb = (uint8_t *)stage;
+                const int csel = from_lane(sel, c.lead_of(anc));
+                uint32_t *sb = (uint32_t *)stage;
                 if (c.lg < Ly::ACT) {
 #pragma unroll
                     for (int j = 0; j < RR; j++)
-                        sb[c.g * n + c.lg + G * j] = (uint8_t)((x >> j) & 1u);
+                        sb[(c.gb + c.g) * n + c.lg + G * j] = (uint32_t)(x >> j) & 1u;
                 }
                 wave_sync();
                 uint32_t pos[RR];
-                map_positions<MN, G, RR>(c.maps() + (mbase + 2 * L + csel) * kMapWords, c.lg, pos);
+                map_positions<MN, G, RR>(c.maps() + (mbase + 2 * L + csel) * kMapWords, c.lg,
+                                         c.stage_addr() + (uint32_t)((c.gb + c.g) * n * 4), pos);
                 typename Ly::Mask y = 0;
 #pragma unroll
                 for (int j = 0; j < RR; j++)
-                    y |= (typename Ly::Mask)(sb[c.g * n + pos[j]] & 1u) << j;
+                    y |= (typename Ly::Mask)(lds_u32(pos[j]) & 1u) << j;
                 x = c.lg < Ly::ACT ? y : (typename Ly::Mask)0;
                 anc = csel % L;
                 wave_sync();
@@ -770,15 +867,15 @@ __device__ __forceinline__ NodeRes<(1 << MN), kWave / L> node(const Ctx<M, R, L>
         }
         return {x, rr.pm, anc};
     } else if constexpr (RN == 1) {
-        return fhtl<M, R, L, MN>(c, A, pm);
+        return fhtl<M, R, L, D, MN>(c, A, pm);
     } else {
         static_assert(RN == MN - 1, "leaf must be RM(1,s) or RM(s-1,s)");
-        return spcl<M, R, L, MN>(c, A, pm);
+        return spcl<M, R, L, D, MN>(c, A, pm);
     }
 }
 
 // Result of one decoder at the root for the path held by this group.
-template <int M, int R, int L>
+template <int M, int R, int L, int D>
 struct RootRes {
     uint64_t xlo, xhi; // codeword masks (internal root: first and second half)
     float pm;
@@ -790,13 +887,12 @@ struct RootRes {
 // through their initial maps; at an internal root in p-FHT mode the 2L
 // candidates are composed maps (initial map of path c mod L, then candidate c).
 // ---------------------------------------------------------------------------
-template <int M, int R, int L>
-__device__ __forceinline__ RootRes<M, R, L> decode_root(const Ctx<M, R, L> &c)
+template <int M, int R, int L, int D>
+__device__ __forceinline__ RootRes<M, R, L, D> decode_root(const Ctx<M, R, L, D> &c)
 {
-    using Sh = Shape<M, R, L>;
+    using Sh = Shape<M, R, L, D>;
     constexpr int N = Sh::N;
     constexpr int G = Sh::G;
-    const float *Y = c.y();
     const uint32_t *maps = c.maps();
     if constexpr (!Sh::ROOT_LEAF) {
         constexpr int h = N / 2;
@@ -804,31 +900,31 @@ __device__ __forceinline__ RootRes<M, R, L> decode_root(const Ctx<M, R, L> &c)
         constexpr int RC = Lc::RR;
         int rmap = c.g;
         if (c.pfht)
-            rmap = 2 * L + perm_select<M, R, L, M>(c, maps + 2 * L * kMapWords, [&](int, uint32_t p) { return Y[p]; });
+            rmap = 2 * L + perm_select<M, R, L, D, M>(c, maps + 2 * L * kMapWords, [&](int) { return c.y_addr(); });
         float C[RC];
         {
             const uint32_t *mp = maps + rmap * kMapWords;
             uint32_t pos[RC];
-            map_positions<M - 1, G, RC>(mp, c.lg, pos);
+            map_positions<M - 1, G, RC>(mp, c.lg, c.y_addr(), pos);
             const uint32_t colh = mp[M - 1];
 #pragma unroll
             for (int j = 0; j < RC; j++)
-                C[j] = f_minsum(Y[pos[j]], Y[pos[j] ^ colh]);
+                C[j] = f_minsum(lds_f32(pos[j]), lds_f32(pos[j] ^ colh));
         }
-        const auto rl = node<M, R, L, M - 1, R - 1, true>(c, C, 0.0f);
+        const auto rl = node<M, R, L, D, M - 1, R - 1, true>(c, C, 0.0f);
         {
-            const uint32_t *mp = maps + from_lane(rmap, rl.anc * G) * kMapWords;
+            const uint32_t *mp = maps + from_lane(rmap, c.lead_of(rl.anc)) * kMapWords;
             uint32_t pos[RC];
-            map_positions<M - 1, G, RC>(mp, c.lg, pos);
+            map_positions<M - 1, G, RC>(mp, c.lg, c.y_addr(), pos);
             const uint32_t colh = mp[M - 1];
 #pragma unroll
             for (int j = 0; j < RC; j++)
-                C[j] = g_func(Y[pos[j]], Y[pos[j] ^ colh], (uint32_t)(rl.x >> j) & 1u);
+                C[j] = g_func(lds_f32(pos[j]), lds_f32(pos[j] ^ colh), (uint32_t)(rl.x >> j) & 1u);
         }
-        const auto rr = node<M, R, L, M - 1, R, false>(c, C, rl.pm);
-        const auto xl = (typename Lc::Mask)from_lane((uint64_t)rl.x, rr.anc * G + c.lg);
-        const int anc = from_lane(rl.anc, rr.anc * G);
-        const int inv = from_lane(rmap, anc * G) + (c.pfht ? 2 * L : L);
+        const auto rr = node<M, R, L, D, M - 1, R, false>(c, C, rl.pm);
+        const auto xl = (typename Lc::Mask)from_lane((uint64_t)rl.x, c.lane_of(rr.anc));
+        const int anc = from_lane(rl.anc, c.lead_of(rr.anc));
+        const int inv = from_lane(rmap, c.lead_of(anc)) + (c.pfht ? 2 * L : L);
         return {(uint64_t)(xl ^ rr.x), (uint64_t)rr.x, rr.pm, inv};
     } else {
         using Ly = Lay<N, G>;
@@ -836,16 +932,16 @@ __device__ __forceinline__ RootRes<M, R, L> decode_root(const Ctx<M, R, L> &c)
         float A[RN];
         {
             uint32_t pos[RN];
-            map_positions<M, G, RN>(maps + c.g * kMapWords, c.lg, pos);
+            map_positions<M, G, RN>(maps + c.g * kMapWords, c.lg, c.y_addr(), pos);
 #pragma unroll
             for (int j = 0; j < RN; j++)
-                A[j] = Y[pos[j]];
+                A[j] = lds_f32(pos[j]);
         }
         NodeRes<N, G> res;
         if constexpr (R == 1)
-            res = fhtl<M, R, L, M>(c, A, 0.0f);
+            res = fhtl<M, R, L, D, M>(c, A, 0.0f);
         else
-            res = spcl<M, R, L, M>(c, A, 0.0f);
+            res = spcl<M, R, L, D, M>(c, A, 0.0f);
         return {(uint64_t)res.x, 0ull, res.pm, L + res.anc};
     }
 }
@@ -853,19 +949,23 @@ __device__ __forceinline__ RootRes<M, R, L> decode_root(const Ctx<M, R, L> &c)
 // ---------------------------------------------------------------------------
 // kernel: one wave per frame (grid-stride), P decoders per frame
 // ---------------------------------------------------------------------------
-template <int M, int R, int L>
-__global__ void __launch_bounds__(256) rm_decode_kernel(KernelArgs args)
+template <int M, int R, int L, int D, int WPE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) rm_decode_kernel(KernelArgs args)
 {
-    using Sh = Shape<M, R, L>;
+    using Sh = Shape<M, R, L, D>;
     constexpr int N = Sh::N;
     constexpr int G = Sh::G;
-    extern __shared__ __align__(16) unsigned char smem[];
     const int wave = (int)(threadIdx.x / kWave);
-    Ctx<M, R, L> c;
-    c.base = smem + wave * Sh::BYTES;
+    Ctx<M, R, L, D> c;
+    c.base = rm_smem + wave * Sh::BYTES;
     c.lane = lane_id();
-    c.g = c.lane / G;
-    c.lg = c.lane % G;
+    {
+        const int gw = c.lane / G;
+        c.g = gw % L;
+        c.gb = gw - c.g;
+        c.ds = gw / L;
+        c.lg = c.lane % G;
+    }
     c.pfht = args.pfht;
     const int64_t stride = (int64_t)gridDim.x * args.waves;
     for (int64_t f = (int64_t)blockIdx.x * args.waves + wave; f < args.n_frames; f += stride) {
@@ -877,30 +977,42 @@ __global__ void __launch_bounds__(256) rm_decode_kernel(KernelArgs args)
         uint64_t *xb = c.xbest();
         if (c.lane < 2 * G)
             xb[c.lane] = 0ull;
-        for (int d = 0; d < args.P; d++) {
-            const uint32_t *mg = args.maps + (size_t)d * args.maps_per_dec * kMapWords;
+        for (int d0 = 0; d0 < args.P; d0 += D) {
+            // the maps of decoders d0 .. d0+D-1 (past P: a copy of the last, result unused)
             wave_sync();
-            for (int i = c.lane; i < args.maps_per_dec * kMapWords; i += kWave)
-                c.maps()[i] = mg[i];
-            wave_sync();
-            const RootRes<M, R, L> r = decode_root<M, R, L>(c);
-            // Alg. 5: first minimum over the list, replace only if strictly smaller
-            float pmin = from_lane(r.pm, 0);
-            int lstar = 0;
 #pragma unroll
-            for (int q = 1; q < L; q++) {
-                const float o = from_lane(r.pm, q * G);
-                if (o < pmin) {
-                    pmin = o;
-                    lstar = q;
-                }
+            for (int t = 0; t < D; t++) {
+                const int dd = d0 + t < args.P ? d0 + t : args.P - 1;
+                const uint32_t *mg = args.maps + (size_t)dd * args.maps_per_dec * kMapWords;
+                uint32_t *ml = c.maps_all() + t * Sh::MAPS_PER_DEC * kMapWords;
+                // columns and offset as byte offsets of float elements
+                for (int i = c.lane; i < args.maps_per_dec * kMapWords; i += kWave)
+                    ml[i] = (i % kMapWords) <= kMapB ? mg[i] << 2 : mg[i];
             }
-            if (pmin < best) {
-                best = pmin;
-                bestmap = d * args.maps_per_dec + from_lane(r.invmap, lstar * G);
-                if (c.g == lstar) {
-                    xb[c.lg] = r.xlo;
-                    xb[G + c.lg] = r.xhi;
+            wave_sync();
+            const RootRes<M, R, L, D> r = decode_root<M, R, L, D>(c);
+            // Alg. 5 in decoder order: first minimum over the list, replace only if strictly smaller
+#pragma unroll
+            for (int t = 0; t < D; t++) {
+                if (d0 + t >= args.P)
+                    break;
+                float pmin = from_lane(r.pm, (t * L) * G);
+                int lstar = 0;
+#pragma unroll
+                for (int q = 1; q < L; q++) {
+                    const float o = from_lane(r.pm, (t * L + q) * G);
+                    if (o < pmin) {
+                        pmin = o;
+                        lstar = q;
+                    }
+                }
+                if (pmin < best) {
+                    best = pmin;
+                    bestmap = (d0 + t) * args.maps_per_dec + from_lane(r.invmap, (t * L + lstar) * G);
+                    if (c.lane / G == t * L + lstar) {
+                        xb[c.lg] = r.xlo;
+                        xb[G + c.lg] = r.xhi;
+                    }
                 }
             }
         }

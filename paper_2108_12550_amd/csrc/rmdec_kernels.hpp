@@ -12,23 +12,30 @@ using LaunchFn = hipError_t (*)(const KernelArgs &args, int blocks, hipStream_t 
 
 struct KernelEntry {
     int m, r, L;
+    int D; // decoders per wavefront
     int lds_bytes_per_wave;
     int maps_per_dec; // maps stored per decoder in p-FHT mode
     LaunchFn launch;
 };
 
-template <int M, int R, int L>
+template <int M, int R, int L, int D, int WPE>
 hipError_t launch_decode(const KernelArgs &args, int blocks, hipStream_t stream)
 {
-    const size_t lds = (size_t)args.waves * Shape<M, R, L>::BYTES;
-    hipLaunchKernelGGL((rm_decode_kernel<M, R, L>), dim3(blocks), dim3(kWave * args.waves), lds, stream, args);
+    const size_t lds = (size_t)args.waves * Shape<M, R, L, D>::BYTES;
+    hipLaunchKernelGGL((rm_decode_kernel<M, R, L, D, WPE>), dim3(blocks), dim3(kWave * args.waves), lds, stream, args);
     return hipGetLastError();
 }
 
-template <int M, int R, int L>
+// Decoders per wavefront: D*L = 8 paths share the 64 lanes (8 lanes per
+// path).  WPE: wavefronts per SIMD the register allocation must allow.
+constexpr int decoders_per_wave(int L) { return L >= 8 ? 1 : 8 / L; }
+constexpr int waves_per_eu(int D) { return D > 1 ? 3 : 5; }
+
+template <int M, int R, int L, int D = decoders_per_wave(L), int WPE = waves_per_eu(D)>
 constexpr KernelEntry entry()
 {
-    return KernelEntry{M, R, L, Shape<M, R, L>::BYTES, Shape<M, R, L>::MAPS_PER_DEC, &launch_decode<M, R, L>};
+    return KernelEntry{M, R, L, D, Shape<M, R, L, D>::BYTES, Shape<M, R, L, D>::MAPS_PER_DEC,
+                       &launch_decode<M, R, L, D, WPE>};
 }
 
 // Each translation unit rmdec_inst_*.hip defines one table.
