@@ -6,6 +6,11 @@ L = 4 per frame, BPSK/AWGN frames at Eb/N0 = 2.0, 2.5, 3.0, 3.5, 4.0 dB,
 kernel launch); steps cycle through the points.  All inputs are generated
 (seeded, synthetic) and copied to HBM before the timed region.
 
+With ``--workload mixed``: one fused persistent launch (graph-replayed) over
+RM(2,7) P=8, RM(2,8) P=16, RM(2,9) P=20 and RM(2,10) P=32, all L = 4, with
+262,144 frames each (1,048,576 per step), Eb/N0 uniform in [2, 4] dB per
+frame; launch choices come from the library's autotuner.
+
 Prints one JSON line.  Diagnostics go to stderr.
 """
 from __future__ import annotations
@@ -44,24 +49,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(sources=KERNEL_SOURCES) -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         h.update(open(f, "rb").read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(path=TRAFFIC_FILE, sources=KERNEL_SOURCES):
     """HBM bytes per launch from the committed rocprofv3 counter runs, or None
     if they were taken on a different version of the kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line:
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash(sources):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -98,12 +103,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
+    ap.add_argument("--workload", choices=("rm29", "mixed"), default="rm29")
     args = ap.parse_args()
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); frames are independent, "
               "so N GPUs would each run this same launch on their share of the frames.", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "mixed":
+        return run_mixed(args)
 
     import torch
     import paper_2108_12550_amd as rmd
@@ -185,6 +194,139 @@ def main():
                                f"p-FHT-FSCL, BPSK/AWGN Eb/N0 2.0-4.0 dB step 0.5",
                    "frames_per_step": n, "ebn0_db": EBN0, "seed": SEED},
         "info_gbit_s": round(fps * K / 1e9, 4),
+        "wall_s_timed": round(wall, 3),
+        "fer": fer,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+# --- fused mixed-code launch -------------------------------------------------
+MIXED_CODES = [(7, 2, 8, 4), (8, 2, 16, 4), (9, 2, 20, 4), (10, 2, 32, 4)]  # (m, r, P, L)
+# per-frame algorithmic ops of each code's decoder set (op model of the
+# paper's complexity count: f/g, LM, FHT, selection, SPC, times P)
+MIXED_OPS = {7: 3.58e4, 8: 1.56e5, 9: 4.27e5, 10: 1.49e6}
+MIXED_KERNEL = "rm_mixed_kernel<3, Code<7,2,4,2>, Code<8,2,4,2>, Code<9,2,4,2>, Code<10,2,4,1>>"
+MIXED_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rm_mixed_c4_traffic.txt")
+MIXED_SOURCES = [os.path.join(ROOT, "paper_2108_12550_amd", "csrc", f)
+                 for f in ("rmdec_device.hpp", "rmdec_mixed.hip")]
+
+
+def mixed_cpu_baseline(data, gpu_bits, budget_s, threads):
+    """Oracle rate on the first frames of each code, budget split evenly; the
+    mix rate is the harmonic combination (equal frame counts per code)."""
+    import oracle
+    per = {}
+    same = True
+    for (m, r, P, L), (x, llr) in zip(MIXED_CODES, data):
+        od = oracle.OracleDecoder(m, r, P, L, seed=SEED)
+        chunk = 16 * threads
+        done, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < budget_s / len(MIXED_CODES):
+            sl = slice(done, done + chunk)
+            bits, _ = od.decode_batch(llr[sl], n_threads=threads)
+            same &= bool(np.array_equal(bits, gpu_bits[m][sl]))
+            done += chunk
+        per[m] = (done, time.perf_counter() - t0)
+    t_frame = sum(dt / n for n, dt in per.values()) / len(per)
+    sample = ", ".join(f"RM(2,{m}): {n} frames in {dt:.1f} s" for m, (n, dt) in per.items())
+    return {"value": 1.0 / t_frame, "unit": "frames/s", "cores": threads, "kind": "oracle",
+            "sample": f"first frames of each code ({sample}); 1:1:1:1 mix rate = 1/mean(time per frame); "
+                      f"{threads} threads; bit-exact vs GPU: {same}"}, same
+
+
+def run_mixed(args):
+    import torch
+    import paper_2108_12550_amd as rmd
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = args.frames
+    log(f"generating 4 x {n} frames (Eb/N0 ~ U[2,4] per frame)")
+    t0 = time.perf_counter()
+    data, dbuf = [], []
+    for m, r, P, L in MIXED_CODES:
+        e = synth.uniform_ebn0(n, 2.0, 4.0, seed=2000 + m)
+        x, llr = synth.frames(m, r, n, e, seed=3000 + m)
+        data.append((x, llr))
+        dbuf.append((torch.from_numpy(llr).to(dev), torch.empty((n, (1 << m) // 8), dtype=torch.uint8, device=dev),
+                     torch.empty((n,), dtype=torch.float32, device=dev)))
+    log(f"inputs ready in {time.perf_counter() - t0:.1f} s")
+    decs = [rmd.Decoder(m, r, P, L, seed=SEED) for m, r, P, L in MIXED_CODES]
+    stream = torch.cuda.Stream(device=dev)
+    mx = rmd.MixedLauncher(max_tiles=4 * n + 16)
+
+    def segs(tiles):
+        return [(d, t, b, p, tf) for d, (t, b, p), tf in zip(decs, dbuf, tiles)]
+
+    t0 = time.perf_counter()
+    tune = mx.autotune(segs([0] * 4), stream=stream, reps=1)
+    log(f"autotune ({time.perf_counter() - t0:.1f} s): {tune}")
+    mx.capture(segs(tune["tile_frames"]), stream)
+
+    # per-code separate launches on the same stream, for comparison and as
+    # the equality check of the fused results
+    sep = [(torch.empty_like(b), torch.empty_like(p)) for _, b, p in dbuf]
+
+    def separate():
+        for d, (t, _, _), (b, p) in zip(decs, dbuf, sep):
+            d.decode(t, out_bits=b, out_metric=p, stream=stream)
+
+    def timed(fn, steps):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(steps):
+            fn()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / max(1, steps)
+
+    for _ in range(args.warmup):
+        mx.replay()
+    t_wall = time.perf_counter()
+    ms_fused = timed(mx.replay, args.steps)
+    wall = time.perf_counter() - t_wall
+    separate()
+    ms_sep = timed(separate, max(1, args.steps // 2))
+    total = 4 * n
+    fps = total / (ms_fused / 1e3)
+    log(f"fused {ms_fused:.3f} ms/step ({fps / 1e6:.3f} M frames/s); separate launches {ms_sep:.3f} ms/step")
+
+    gpu_bits, fer, same_sep = {}, {}, True
+    for (m, r, P, L), (x, _), (_, b, p), (sb, sp) in zip(MIXED_CODES, data, dbuf, sep):
+        bb = b.cpu().numpy()
+        gpu_bits[m] = bb
+        same_sep &= bool(np.array_equal(bb, sb.cpu().numpy()) and torch.equal(p, sp))
+        fer[f"RM(2,{m})"] = float(np.mean(np.any(synth.unpack_bits(bb, 1 << m) != x, axis=1)))
+    log(f"FER per code: {fer}; fused == separate: {same_sep}")
+
+    ops = sum(MIXED_OPS[m] for m, *_ in MIXED_CODES) * n
+    achieved = ops / (ms_fused / 1e3) / 1e12
+    byts = sum(4 * (1 << m) + (1 << m) // 8 + 4 for m, *_ in MIXED_CODES) * n
+    roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(ALU_PEAK_TOPS, 4), "unit": "TFLOP/s",
+            "frac": round(achieved / ALU_PEAK_TOPS, 5),
+            "traffic": measured_traffic(MIXED_TRAFFIC_FILE, MIXED_SOURCES),
+            "kernel": MIXED_KERNEL, "avg_launch_ms": round(ms_fused, 4),
+            "hbm_gbs_algorithmic": round(byts / (ms_fused / 1e3) / 1e9, 2)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = min(16, os.cpu_count() or 1)
+        cpu, _ = mixed_cpu_baseline(data, gpu_bits, args.cpu_budget, threads)
+        log(f"cpu_baseline: {cpu}")
+    K = {m: synth.code_dimension(m, r) for m, r, *_ in MIXED_CODES}
+    out = {
+        "metric": METRIC, "value": round(fps, 1), "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_fused, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "fused mixed-code launch: RM(7,2) P=8, RM(8,2) P=16, RM(9,2) P=20, RM(10,2) P=32, "
+                               "all L=4, 1:1:1:1, Eb/N0 ~ U[2,4] dB per frame, hipGraph replay",
+                   "frames_per_step": total, "seed": SEED, "tuning": tune},
+        "info_gbit_s": round(sum(K.values()) * n / (ms_fused / 1e3) / 1e9, 4),
+        "separate_launches_ms_per_step": round(ms_sep, 4),
+        "fused_equals_separate": same_sep,
         "wall_s_timed": round(wall, 3),
         "fer": fer,
         "roofline": roof,

@@ -120,6 +120,93 @@ int rm_supported(int m, int r, int L, int perm_mode);
 /* Message of the last error on this thread ("" if none). */
 const char *rm_last_error(void);
 
+/*
+ * Fused mixed-code launch: frames of several codes (decoders created above)
+ * decoded by ONE persistent kernel launch.  The host cuts every segment into
+ * runs of `tile_frames` frames and interleaves the runs of all segments
+ * round-robin into one work queue (equal segment sizes give a 1:1:...:1
+ * interleave); the persistent grid drains the queue.  Per frame the result
+ * is exactly that of rm_decode_batch with the segment's decoder (Alg. 5 over
+ * Alg. 2-4 and the SPC rules).
+ */
+typedef struct rm_mixed rm_mixed;
+
+typedef struct rm_segment {
+    const rm_decoder *dec; /* decoder of this segment's code (its tables, P, L)  */
+    const float *llr;      /* device, n_frames x N float32, frame-major          */
+    int64_t n_frames;      /* >= 0                                               */
+    uint8_t *out_bits;     /* device, n_frames x N/8 bytes (as rm_decode_batch)  */
+    float *out_metric;     /* device, n_frames float32, or NULL                  */
+    int tile_frames;       /* frames per queue entry, 1..64; 0 = library default */
+} rm_segment;
+
+#define RM_MIXED_MAX_SEGMENTS 8
+
+/*
+ * Create a mixed launcher on the current device: a device work queue of up to
+ * max_tiles entries (16 bytes each) and a pinned host staging copy of it.
+ * Returns NULL on error (see rm_last_error()).
+ */
+rm_mixed *rm_mixed_create(int64_t max_tiles);
+
+/* 1 if (m, r, L) is compiled into the fused kernel, else 0.  Host only. */
+int rm_mixed_supported(int m, int r, int L);
+
+/* Bind a hipStream_t (as void*) for later launches and graph captures. */
+int rm_mixed_set_stream(rm_mixed *mx, void *hip_stream);
+
+/* Persistent grid size: blocks and waves per block (0 = library choice). */
+int rm_mixed_set_grid(rm_mixed *mx, int blocks, int waves_per_block);
+
+/*
+ * Queue the segments (1..RM_MIXED_MAX_SEGMENTS) on the bound stream: an
+ * asynchronous upload of the queue entries, a reset of the queue head and
+ * one persistent launch.  Returns without waiting (it waits only for the
+ * previous call's upload to have left the staging buffer).  Successive calls
+ * reuse one device queue, so all calls on one launcher must go to one stream
+ * (or be ordered by the caller).  Segments whose code is not compiled into
+ * the fused kernel give RM_E_UNSUPPORTED; more entries than max_tiles give
+ * RM_E_INVAL; host pointers give RM_E_PTR.  Nothing is queued on error.
+ */
+int rm_mixed_decode(rm_mixed *mx, const rm_segment *segs, int n_segs);
+
+/*
+ * Record the launch of rm_mixed_decode for these segments (same pointers
+ * and sizes) as a hipGraph on the bound stream, which must not be the null
+ * stream; rm_mixed_replay launches it again on the bound stream.  The graph
+ * owns a device queue of its own, filled once at capture (a synchronous
+ * copy), so later rm_mixed_decode calls do not disturb it.  The recorded
+ * steps are: reset of the queue head (a kernel, not a memset) and the
+ * persistent decode kernel.  Re-capturing replaces the graph.  The segments'
+ * buffers and decoders must stay valid while the graph may be replayed.
+ */
+int rm_mixed_capture(rm_mixed *mx, const rm_segment *segs, int n_segs);
+int rm_mixed_replay(rm_mixed *mx);
+
+/* Launch choices of the fused kernel found by rm_mixed_autotune. */
+typedef struct rm_mixed_tuning {
+    int blocks;                                /* persistent grid (0 = from occupancy)   */
+    int waves_per_block;                       /* chosen wavefronts per block            */
+    int tile_frames[RM_MIXED_MAX_SEGMENTS];    /* chosen frames per queue entry, per segment */
+    float ms;                                  /* average launch time of the best choice */
+    int trials;                                /* configurations timed                   */
+} rm_mixed_tuning;
+
+/*
+ * Autotuner: time rm_mixed_decode on these segments (their outputs are
+ * overwritten) for waves per block in {1, 2, 4} and frames per queue entry
+ * in {1, 2, 4, 8, 16} -- first one value for all segments, then each
+ * segment's own value with the others held -- one warm-up and `reps` timed
+ * launches (1..100) per choice.  Blocks on the bound stream.  Sets the
+ * launcher's waves per block to the best choice and returns all choices in
+ * *out; the caller puts out->tile_frames[i] into segment i.  The decoded
+ * results do not depend on any of these choices.
+ */
+int rm_mixed_autotune(rm_mixed *mx, const rm_segment *segs, int n_segs, int reps, rm_mixed_tuning *out);
+
+/* Release after the work queued on its stream completes.  NULL-safe. */
+void rm_mixed_destroy(rm_mixed *mx);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,14 +11,19 @@ from __future__ import annotations
 from math import comb
 
 from . import _lib
-from ._lib import (RM_E_HIP, RM_E_INVAL, RM_E_NOMEM, RM_E_PTR, RM_E_UNSUPPORTED, RM_OK, RM_PERM_NONE,
-                   RM_PERM_PFHT, rm_config, rm_decode_batch, rm_decoder_create, rm_decoder_create_ex,
-                   rm_decoder_destroy, rm_decoder_info, rm_decoder_set_stream, rm_last_error, rm_perm_tables,
-                   rm_supported)
+from ._lib import (RM_E_HIP, RM_E_INVAL, RM_E_NOMEM, RM_E_PTR, RM_E_UNSUPPORTED, RM_MIXED_MAX_SEGMENTS, RM_OK,
+                   RM_PERM_NONE, RM_PERM_PFHT, rm_config, rm_decode_batch, rm_decoder_create, rm_decoder_create_ex,
+                   rm_decoder_destroy, rm_decoder_info, rm_decoder_set_stream, rm_last_error, rm_mixed_autotune,
+                   rm_mixed_capture, rm_mixed_create, rm_mixed_decode, rm_mixed_destroy, rm_mixed_replay,
+                   rm_mixed_set_grid, rm_mixed_set_stream, rm_mixed_supported, rm_mixed_tuning, rm_perm_tables,
+                   rm_segment, rm_supported)
 
-__all__ = ["Decoder", "perm_tables", "code_dimension", "RM_PERM_NONE", "RM_PERM_PFHT", "rm_config",
-           "rm_decode_batch", "rm_decoder_create", "rm_decoder_create_ex", "rm_decoder_destroy",
-           "rm_decoder_info", "rm_decoder_set_stream", "rm_last_error", "rm_perm_tables", "rm_supported"]
+__all__ = ["Decoder", "MixedLauncher", "perm_tables", "code_dimension", "RM_PERM_NONE", "RM_PERM_PFHT",
+           "RM_MIXED_MAX_SEGMENTS", "rm_config", "rm_segment", "rm_decode_batch", "rm_decoder_create",
+           "rm_decoder_create_ex", "rm_decoder_destroy", "rm_decoder_info", "rm_decoder_set_stream",
+           "rm_last_error", "rm_perm_tables", "rm_supported", "rm_mixed_create", "rm_mixed_supported",
+           "rm_mixed_set_stream", "rm_mixed_set_grid", "rm_mixed_decode", "rm_mixed_capture",
+           "rm_mixed_replay", "rm_mixed_autotune", "rm_mixed_tuning", "rm_mixed_destroy"]
 
 
 def code_dimension(m: int, r: int) -> int:
@@ -80,6 +85,85 @@ class Decoder:
         if rc != RM_OK:
             raise RMError(rc, rm_last_error())
         return out_bits, out_metric
+
+
+class MixedLauncher:
+    """One persistent launch over frames of several codes (rm_mixed_* of the C ABI).
+
+    A segment is ``(decoder, llr, out_bits, out_metric, tile_frames)``: a
+    ``Decoder`` of a code compiled into the fused kernel, its (n, N) float32
+    LLRs, (n, N/8) uint8 and (n,) float32 outputs (CUDA tensors; out_metric
+    may be None) and the frames per queue entry (0 = library default).
+    """
+
+    def __init__(self, max_tiles: int = 1 << 20, blocks: int = 0, waves_per_block: int = 0):
+        self._h = rm_mixed_create(max_tiles)
+        if not self._h:
+            raise RMError(-1, rm_last_error())
+        self._check(rm_mixed_set_grid(self._h, blocks, waves_per_block))
+        self._held = None  # tensors a captured graph refers to
+
+    @staticmethod
+    def supported(m: int, r: int, L: int) -> bool:
+        return rm_mixed_supported(m, r, L)
+
+    def _check(self, rc):
+        if rc != RM_OK:
+            raise RMError(rc, rm_last_error())
+
+    def set_grid(self, blocks: int, waves_per_block: int):
+        self._check(rm_mixed_set_grid(self._h, blocks, waves_per_block))
+
+    def _segs(self, segments):
+        import torch
+        out = []
+        for dec, llr, bits, metric, tf in segments:
+            if not (llr.is_cuda and llr.dtype == torch.float32 and llr.is_contiguous()):
+                raise ValueError("llr must be a contiguous float32 CUDA tensor")
+            n = llr.numel() // dec.N
+            if bits.numel() < n * dec.N // 8 or (metric is not None and metric.numel() < n):
+                raise ValueError("output tensors too small")
+            out.append(rm_segment(dec._h, llr.data_ptr(), n, bits.data_ptr(),
+                                  metric.data_ptr() if metric is not None else None, tf))
+        return out
+
+    def _bind(self, stream):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self._check(rm_mixed_set_stream(self._h, s.cuda_stream))
+
+    def decode(self, segments, stream=None):
+        """Queue one fused launch over the segments on ``stream``."""
+        self._bind(stream)
+        self._check(rm_mixed_decode(self._h, self._segs(segments)))
+
+    def capture(self, segments, stream):
+        """Record the fused launch for these segments as a graph (replay())."""
+        self._bind(stream)
+        self._check(rm_mixed_capture(self._h, self._segs(segments)))
+        self._held = list(segments)
+
+    def replay(self):
+        self._check(rm_mixed_replay(self._h))
+
+    def autotune(self, segments, stream=None, reps: int = 2) -> dict:
+        """Time launch choices on these segments (outputs overwritten) and keep
+        the best; returns {"waves_per_block", "tile_frames", "ms", "trials"}.
+        The segments' own tile_frames entries are ignored."""
+        self._bind(stream)
+        rc, t = rm_mixed_autotune(self._h, self._segs(segments), reps)
+        self._check(rc)
+        return {"waves_per_block": t.waves_per_block, "blocks": t.blocks,
+                "tile_frames": [t.tile_frames[i] for i in range(len(segments))], "ms": t.ms, "trials": t.trials}
+
+    def close(self):
+        if getattr(self, "_h", 0):
+            rm_mixed_destroy(self._h)
+            self._h = 0
+        self._held = None
+
+    def __del__(self):
+        self.close()
 
 
 def perm_tables(m: int, r: int, P: int, L: int, seed: int, perm_mode: int = RM_PERM_PFHT):

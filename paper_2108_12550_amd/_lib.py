@@ -22,7 +22,11 @@ RM_PERM_NONE = 0
 RM_PERM_PFHT = 1
 
 EXPORTED = ("rm_decoder_create", "rm_decoder_create_ex", "rm_decode_batch", "rm_decoder_destroy",
-            "rm_decoder_set_stream", "rm_decoder_info", "rm_perm_tables", "rm_supported", "rm_last_error")
+            "rm_decoder_set_stream", "rm_decoder_info", "rm_perm_tables", "rm_supported", "rm_last_error",
+            "rm_mixed_create", "rm_mixed_supported", "rm_mixed_set_stream", "rm_mixed_set_grid", "rm_mixed_decode",
+            "rm_mixed_capture", "rm_mixed_replay", "rm_mixed_autotune", "rm_mixed_destroy")
+
+RM_MIXED_MAX_SEGMENTS = 8
 
 
 class rm_config(ctypes.Structure):
@@ -36,6 +40,17 @@ class rm_info(ctypes.Structure):
                 ("n_perm_nodes", ctypes.c_int), ("maps_per_decoder", ctypes.c_int),
                 ("waves_per_block", ctypes.c_int), ("lds_bytes_per_wave", ctypes.c_size_t),
                 ("table_bytes", ctypes.c_size_t)]
+
+
+class rm_segment(ctypes.Structure):
+    _fields_ = [("dec", ctypes.c_void_p), ("llr", ctypes.c_void_p), ("n_frames", ctypes.c_int64),
+                ("out_bits", ctypes.c_void_p), ("out_metric", ctypes.c_void_p), ("tile_frames", ctypes.c_int)]
+
+
+class rm_mixed_tuning(ctypes.Structure):
+    _fields_ = [("blocks", ctypes.c_int), ("waves_per_block", ctypes.c_int),
+                ("tile_frames", ctypes.c_int * RM_MIXED_MAX_SEGMENTS), ("ms", ctypes.c_float),
+                ("trials", ctypes.c_int)]
 
 
 _lib = None
@@ -71,6 +86,23 @@ def load() -> ctypes.CDLL:
     L.rm_supported.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     L.rm_last_error.restype = ctypes.c_char_p
     L.rm_last_error.argtypes = []
+    L.rm_mixed_create.restype = vp
+    L.rm_mixed_create.argtypes = [ctypes.c_int64]
+    L.rm_mixed_supported.restype = ctypes.c_int
+    L.rm_mixed_supported.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.rm_mixed_set_stream.restype = ctypes.c_int
+    L.rm_mixed_set_stream.argtypes = [vp, vp]
+    L.rm_mixed_set_grid.restype = ctypes.c_int
+    L.rm_mixed_set_grid.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    for f in ("rm_mixed_decode", "rm_mixed_capture"):
+        getattr(L, f).restype = ctypes.c_int
+        getattr(L, f).argtypes = [vp, P(rm_segment), ctypes.c_int]
+    L.rm_mixed_replay.restype = ctypes.c_int
+    L.rm_mixed_replay.argtypes = [vp]
+    L.rm_mixed_autotune.restype = ctypes.c_int
+    L.rm_mixed_autotune.argtypes = [vp, P(rm_segment), ctypes.c_int, ctypes.c_int, P(rm_mixed_tuning)]
+    L.rm_mixed_destroy.restype = None
+    L.rm_mixed_destroy.argtypes = [vp]
     _lib = L
     return L
 
@@ -117,3 +149,48 @@ def rm_perm_tables(m: int, r: int, P: int, L: int, seed: int, perm_mode: int, ca
 
 def rm_supported(m: int, r: int, L: int, perm_mode: int) -> bool:
     return bool(load().rm_supported(m, r, L, perm_mode))
+
+
+def rm_mixed_create(max_tiles: int) -> int:
+    return load().rm_mixed_create(max_tiles) or 0
+
+
+def rm_mixed_supported(m: int, r: int, L: int) -> bool:
+    return bool(load().rm_mixed_supported(m, r, L))
+
+
+def rm_mixed_set_stream(mx: int, stream_handle: int) -> int:
+    return load().rm_mixed_set_stream(mx, stream_handle or None)
+
+
+def rm_mixed_set_grid(mx: int, blocks: int, waves_per_block: int) -> int:
+    return load().rm_mixed_set_grid(mx, blocks, waves_per_block)
+
+
+def _segments(segs):
+    arr = (rm_segment * max(1, len(segs)))()
+    for i, s in enumerate(segs):
+        arr[i] = s
+    return arr
+
+
+def rm_mixed_decode(mx: int, segs) -> int:
+    return load().rm_mixed_decode(mx, _segments(segs), len(segs))
+
+
+def rm_mixed_capture(mx: int, segs) -> int:
+    return load().rm_mixed_capture(mx, _segments(segs), len(segs))
+
+
+def rm_mixed_replay(mx: int) -> int:
+    return load().rm_mixed_replay(mx)
+
+
+def rm_mixed_autotune(mx: int, segs, reps: int):
+    out = rm_mixed_tuning()
+    rc = load().rm_mixed_autotune(mx, _segments(segs), len(segs), reps, ctypes.byref(out))
+    return rc, out
+
+
+def rm_mixed_destroy(mx: int) -> None:
+    load().rm_mixed_destroy(mx)

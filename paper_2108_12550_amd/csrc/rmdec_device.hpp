@@ -947,17 +947,17 @@ __device__ __forceinline__ RootRes<M, R, L, D> decode_root(const Ctx<M, R, L, D>
 }
 
 // ---------------------------------------------------------------------------
-// kernel: one wave per frame (grid-stride), P decoders per frame
+// One frame: the P decoders of Alg. 5, then the winner back in channel order.
+// The calling wavefront owns the LDS slice at `slice`.
 // ---------------------------------------------------------------------------
-template <int M, int R, int L, int D, int WPE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) rm_decode_kernel(KernelArgs args)
+template <int M, int R, int L, int D>
+__device__ __forceinline__ void decode_frame(const KernelArgs &args, int64_t f, unsigned char *slice)
 {
     using Sh = Shape<M, R, L, D>;
     constexpr int N = Sh::N;
     constexpr int G = Sh::G;
-    const int wave = (int)(threadIdx.x / kWave);
     Ctx<M, R, L, D> c;
-    c.base = rm_smem + wave * Sh::BYTES;
+    c.base = slice;
     c.lane = lane_id();
     {
         const int gw = c.lane / G;
@@ -967,95 +967,180 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
         c.lg = c.lane % G;
     }
     c.pfht = args.pfht;
-    const int64_t stride = (int64_t)gridDim.x * args.waves;
-    for (int64_t f = (int64_t)blockIdx.x * args.waves + wave; f < args.n_frames; f += stride) {
-        const float *src = args.llr + f * N;
-        for (int i = c.lane; i < N; i += kWave)
-            c.y()[i] = src[i];
-        float best = __builtin_inff();
-        int bestmap = 0;
-        uint64_t *xb = c.xbest();
-        if (c.lane < 2 * G)
-            xb[c.lane] = 0ull;
-        for (int d0 = 0; d0 < args.P; d0 += D) {
-            // the maps of decoders d0 .. d0+D-1 (past P: a copy of the last, result unused)
-            wave_sync();
+    const float *src = args.llr + f * N;
+    wave_sync();
+    for (int i = c.lane; i < N; i += kWave)
+        c.y()[i] = src[i];
+    float best = __builtin_inff();
+    int bestmap = 0;
+    uint64_t *xb = c.xbest();
+    if (c.lane < 2 * G)
+        xb[c.lane] = 0ull;
+    for (int d0 = 0; d0 < args.P; d0 += D) {
+        // the maps of decoders d0 .. d0+D-1 (past P: a copy of the last, result unused)
+        wave_sync();
 #pragma unroll
-            for (int t = 0; t < D; t++) {
-                const int dd = d0 + t < args.P ? d0 + t : args.P - 1;
-                const uint32_t *mg = args.maps + (size_t)dd * args.maps_per_dec * kMapWords;
-                uint32_t *ml = c.maps_all() + t * Sh::MAPS_PER_DEC * kMapWords;
-                // columns and offset as byte offsets of float elements
-                for (int i = c.lane; i < args.maps_per_dec * kMapWords; i += kWave)
-                    ml[i] = (i % kMapWords) <= kMapB ? mg[i] << 2 : mg[i];
-            }
-            wave_sync();
-            const RootRes<M, R, L, D> r = decode_root<M, R, L, D>(c);
-            // Alg. 5 in decoder order: first minimum over the list, replace only if strictly smaller
+        for (int t = 0; t < D; t++) {
+            const int dd = d0 + t < args.P ? d0 + t : args.P - 1;
+            const uint32_t *mg = args.maps + (size_t)dd * args.maps_per_dec * kMapWords;
+            uint32_t *ml = c.maps_all() + t * Sh::MAPS_PER_DEC * kMapWords;
+            // columns and offset as byte offsets of float elements
+            for (int i = c.lane; i < args.maps_per_dec * kMapWords; i += kWave)
+                ml[i] = (i % kMapWords) <= kMapB ? mg[i] << 2 : mg[i];
+        }
+        wave_sync();
+        const RootRes<M, R, L, D> r = decode_root<M, R, L, D>(c);
+        // Alg. 5 in decoder order: first minimum over the list, replace only if strictly smaller
 #pragma unroll
-            for (int t = 0; t < D; t++) {
-                if (d0 + t >= args.P)
-                    break;
-                float pmin = from_lane(r.pm, (t * L) * G);
-                int lstar = 0;
+        for (int t = 0; t < D; t++) {
+            if (d0 + t >= args.P)
+                break;
+            float pmin = from_lane(r.pm, (t * L) * G);
+            int lstar = 0;
 #pragma unroll
-                for (int q = 1; q < L; q++) {
-                    const float o = from_lane(r.pm, (t * L + q) * G);
-                    if (o < pmin) {
-                        pmin = o;
-                        lstar = q;
-                    }
+            for (int q = 1; q < L; q++) {
+                const float o = from_lane(r.pm, (t * L + q) * G);
+                if (o < pmin) {
+                    pmin = o;
+                    lstar = q;
                 }
-                if (pmin < best) {
-                    best = pmin;
-                    bestmap = (d0 + t) * args.maps_per_dec + from_lane(r.invmap, (t * L + lstar) * G);
-                    if (c.lane / G == t * L + lstar) {
-                        xb[c.lg] = r.xlo;
-                        xb[G + c.lg] = r.xhi;
-                    }
+            }
+            if (pmin < best) {
+                best = pmin;
+                bestmap = (d0 + t) * args.maps_per_dec + from_lane(r.invmap, (t * L + lstar) * G);
+                if (c.lane / G == t * L + lstar) {
+                    xb[c.lg] = r.xlo;
+                    xb[G + c.lg] = r.xhi;
                 }
             }
         }
-        wave_sync();
-        // the winner back in channel order, packed
-        const uint32_t *mi = args.maps + (size_t)bestmap * kMapWords;
-        uint32_t col[M + 1];
+    }
+    wave_sync();
+    // the winner back in channel order, packed
+    const uint32_t *mi = args.maps + (size_t)bestmap * kMapWords;
+    uint32_t col[M + 1];
+#pragma unroll
+    for (int k = 0; k < M; k++)
+        col[k] = mi[k];
+    col[M] = mi[kMapB];
+    uint8_t *ob = args.out_bits + f * (N / 8);
+#pragma unroll
+    for (int j0 = 0; j0 < N; j0 += kWave) {
+        const uint32_t j = (uint32_t)(j0 + c.lane);
+        uint32_t e = col[M];
 #pragma unroll
         for (int k = 0; k < M; k++)
-            col[k] = mi[k];
-        col[M] = mi[kMapB];
-        uint8_t *ob = args.out_bits + f * (N / 8);
-#pragma unroll
-        for (int j0 = 0; j0 < N; j0 += kWave) {
-            const uint32_t j = (uint32_t)(j0 + c.lane);
-            uint32_t e = col[M];
-#pragma unroll
-            for (int k = 0; k < M; k++)
-                e ^= ((j >> k) & 1u) ? col[k] : 0u;
-            uint32_t bit = 0;
-            if (j < (uint32_t)N) {
-                e &= (uint32_t)(N - 1);
-                if constexpr (!Sh::ROOT_LEAF) {
-                    constexpr uint32_t h = N / 2;
-                    const uint32_t ee = e < h ? e : e - h;
-                    const uint64_t w = xb[(e < h ? 0 : G) + (ee % G)];
-                    bit = (uint32_t)(w >> (ee / G)) & 1u;
-                } else {
-                    bit = (uint32_t)(xb[e % G] >> (e / G)) & 1u;
-                }
-            }
-            const uint64_t mask = __ballot(bit != 0);
-            if constexpr (N >= kWave) {
-                if (c.lane == 0)
-                    *(uint64_t *)(ob + j0 / 8) = mask;
+            e ^= ((j >> k) & 1u) ? col[k] : 0u;
+        uint32_t bit = 0;
+        if (j < (uint32_t)N) {
+            e &= (uint32_t)(N - 1);
+            if constexpr (!Sh::ROOT_LEAF) {
+                constexpr uint32_t h = N / 2;
+                const uint32_t ee = e < h ? e : e - h;
+                const uint64_t w = xb[(e < h ? 0 : G) + (ee % G)];
+                bit = (uint32_t)(w >> (ee / G)) & 1u;
             } else {
-                if (c.lane < N / 8)
-                    ob[c.lane] = (uint8_t)(mask >> (8 * c.lane));
+                bit = (uint32_t)(xb[e % G] >> (e / G)) & 1u;
             }
         }
-        if (args.out_pm && c.lane == 0)
-            args.out_pm[f] = best;
-        wave_sync();
+        const uint64_t mask = __ballot(bit != 0);
+        if constexpr (N >= kWave) {
+            if (c.lane == 0)
+                *(uint64_t *)(ob + j0 / 8) = mask;
+        } else {
+            if (c.lane < N / 8)
+                ob[c.lane] = (uint8_t)(mask >> (8 * c.lane));
+        }
+    }
+    if (args.out_pm && c.lane == 0)
+        args.out_pm[f] = best;
+    wave_sync();
+}
+
+// ---------------------------------------------------------------------------
+// batched kernel: one wave per frame (grid-stride)
+// ---------------------------------------------------------------------------
+template <int M, int R, int L, int D, int WPE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) rm_decode_kernel(KernelArgs args)
+{
+    using Sh = Shape<M, R, L, D>;
+    const int wave = (int)(threadIdx.x / kWave);
+    unsigned char *slice = rm_smem + wave * Sh::BYTES;
+    const int64_t stride = (int64_t)gridDim.x * args.waves;
+    for (int64_t f = (int64_t)blockIdx.x * args.waves + wave; f < args.n_frames; f += stride)
+        decode_frame<M, R, L, D>(args, f, slice);
+}
+
+// ---------------------------------------------------------------------------
+// Fused mixed-code launch: a persistent grid drains a queue of tiles, each a
+// run of frames of one segment (one code, one decoder set); the code of a
+// segment selects which compiled decoder runs.
+// ---------------------------------------------------------------------------
+constexpr int kMaxSegments = 8;
+
+struct Tile {
+    uint32_t seg;   // segment index
+    uint32_t first; // first frame of the run
+    uint32_t count; // frames in the run
+    uint32_t pad;
+};
+
+struct MixedArgs {
+    KernelArgs seg[kMaxSegments]; // per segment: its frames, outputs and decoder tables
+    int code[kMaxSegments];       // index of the segment's code in the kernel's code list
+    const Tile *tiles;
+    uint32_t n_tiles;
+    uint32_t *head; // next tile to take; reset to 0 before every launch
+    int waves;
+};
+
+template <int M_, int R_, int L_, int D_>
+struct Code {
+    static constexpr int M = M_, R = R_, L = L_, D = D_;
+    using Sh = Shape<M_, R_, L_, D_>;
+};
+
+// LDS slice of one wave in the fused kernel: the largest footprint of the
+// codes, rounded up to a multiple of the largest 4N, so that every code's
+// slice base stays aligned to its own 4N (the XOR-folded gathers need it).
+template <class... Codes>
+struct MaxBytes {
+    static constexpr int cmax(int a, int b) { return a > b ? a : b; }
+    template <class... T>
+    static constexpr int vmax(T... v)
+    {
+        int r = 0;
+        ((r = cmax(r, v)), ...);
+        return r;
+    }
+    static constexpr int align = vmax(4 * Codes::Sh::N...);
+    static constexpr int value = (vmax(Codes::Sh::BYTES...) + align - 1) / align * align;
+};
+
+template <class C>
+__device__ __forceinline__ void run_tile(const KernelArgs &a, const Tile &t, unsigned char *slice)
+{
+    for (uint32_t k = 0; k < t.count; k++)
+        decode_frame<C::M, C::R, C::L, C::D>(a, (int64_t)t.first + k, slice);
+}
+
+template <int WPE, class... Codes>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) rm_mixed_kernel(MixedArgs a)
+{
+    const int wave = (int)(threadIdx.x / kWave);
+    unsigned char *slice = rm_smem + wave * MaxBytes<Codes...>::value;
+    while (true) {
+        uint32_t t = 0;
+        if (lane_id() == 0)
+            t = atomicAdd(a.head, 1u);
+        t = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
+        if (t >= a.n_tiles)
+            break; // every wave ends once the queue is drained
+        const Tile tile = a.tiles[t];
+        const int code = a.code[tile.seg];
+        const KernelArgs &ka = a.seg[tile.seg];
+        int idx = 0;
+        ((code == idx++ ? (run_tile<Codes>(ka, tile, slice), 0) : 0), ...);
     }
 }
 

@@ -11,12 +11,12 @@
 #include <vector>
 
 #include "rmdec.h"
+#include "rmdec_internal.hpp"
 #include "rmdec_kernels.hpp"
 
 using namespace rmdec;
 
-namespace {
-
+namespace rmdec {
 thread_local std::string g_err;
 
 int fail(int code, const std::string &msg)
@@ -24,6 +24,38 @@ int fail(int code, const std::string &msg)
     g_err = msg;
     return code;
 }
+
+int check_device_ptr(const void *p, const char *name)
+{
+    hipPointerAttribute_t a;
+    memset(&a, 0, sizeof a);
+    hipError_t e = hipPointerGetAttributes(&a, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(RM_E_PTR, std::string(name) + " is not device memory");
+    }
+    if (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged)
+        return fail(RM_E_PTR, std::string(name) + " is not device memory");
+    return RM_OK;
+}
+
+KernelArgs batch_args(const rm_decoder *d, const float *llr, int64_t n_frames, uint8_t *out_bits, float *out_metric)
+{
+    KernelArgs a;
+    a.llr = llr;
+    a.out_bits = out_bits;
+    a.out_pm = out_metric;
+    a.maps = d->d_maps;
+    a.n_frames = n_frames;
+    a.P = d->cfg.P;
+    a.maps_per_dec = d->maps_per_dec;
+    a.pfht = d->cfg.perm_mode == RM_PERM_PFHT;
+    a.waves = d->cfg.waves_per_block;
+    return a;
+}
+} // namespace rmdec
+
+namespace {
 
 // SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): Weyl increment, then mix.
 struct SplitMix64 {
@@ -192,15 +224,6 @@ int binom_sum(int m, int r)
 
 } // namespace
 
-struct rm_decoder {
-    rm_config cfg;
-    int N, K, nperm, maps_per_dec;
-    const KernelEntry *kern;
-    uint32_t *d_maps;
-    size_t table_bytes;
-    hipStream_t stream;
-    int device;
-};
 
 extern "C" {
 
@@ -374,20 +397,6 @@ int rm_decoder_info(const rm_decoder *d, rm_info *out)
     return RM_OK;
 }
 
-static int check_device_ptr(const void *p, const char *name)
-{
-    hipPointerAttribute_t a;
-    memset(&a, 0, sizeof a);
-    hipError_t e = hipPointerGetAttributes(&a, p);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(RM_E_PTR, std::string(name) + " is not device memory");
-    }
-    if (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged)
-        return fail(RM_E_PTR, std::string(name) + " is not device memory");
-    return RM_OK;
-}
-
 int rm_decode_batch(rm_decoder *d, const float *llr, int64_t n_frames, uint8_t *out_bits, float *out_metric)
 {
     if (!d)
@@ -405,16 +414,7 @@ int rm_decode_batch(rm_decoder *d, const float *llr, int64_t n_frames, uint8_t *
         rc = check_device_ptr(out_metric, "out_metric");
     if (rc != RM_OK)
         return rc;
-    KernelArgs a;
-    a.llr = llr;
-    a.out_bits = out_bits;
-    a.out_pm = out_metric;
-    a.maps = d->d_maps;
-    a.n_frames = n_frames;
-    a.P = d->cfg.P;
-    a.maps_per_dec = d->maps_per_dec;
-    a.pfht = d->cfg.perm_mode == RM_PERM_PFHT;
-    a.waves = d->cfg.waves_per_block;
+    KernelArgs a = batch_args(d, llr, n_frames, out_bits, out_metric);
     const int64_t blocks64 = (n_frames + a.waves - 1) / a.waves;
     const int blocks = (int)(blocks64 > (1 << 30) ? (1 << 30) : blocks64);
     hipError_t e = d->kern->launch(a, blocks, d->stream);

@@ -1,0 +1,26 @@
+// rmdec_internal.hpp -- library-internal declarations shared by the host units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "rmdec.h"
+#include "rmdec_kernels.hpp"
+
+struct rm_decoder {
+    rm_config cfg;
+    int N, K, nperm, maps_per_dec;
+    const rmdec::KernelEntry *kern;
+    uint32_t *d_maps;
+    size_t table_bytes;
+    hipStream_t stream;
+    int device;
+};
+
+namespace rmdec {
+extern thread_local std::string g_err;
+int fail(int code, const std::string &msg);
+int check_device_ptr(const void *p, const char *name);
+KernelArgs batch_args(const rm_decoder *d, const float *llr, int64_t n_frames, uint8_t *out_bits, float *out_metric);
+} // namespace rmdec

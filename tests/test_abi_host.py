@@ -91,3 +91,31 @@ def test_create_without_device_fails_cleanly():
 def test_null_decoder_calls():
     assert _lib.load().rm_decode_batch(None, None, 1, None, None) == _lib.RM_E_INVAL
     assert _lib.load().rm_decoder_set_stream(None, None) == _lib.RM_E_INVAL
+
+
+def test_mixed_codes_compiled_into_fused_kernel():
+    for m in (7, 8, 9, 10):
+        assert rmd.rm_mixed_supported(m, 2, 4)
+    assert not rmd.rm_mixed_supported(9, 2, 1)
+    assert not rmd.rm_mixed_supported(8, 3, 8)
+
+
+def test_mixed_null_and_invalid_calls():
+    lib = _lib.load()
+    segs = (_lib.rm_segment * 1)()
+    assert lib.rm_mixed_decode(None, segs, 1) == _lib.RM_E_INVAL
+    assert lib.rm_mixed_capture(None, segs, 1) == _lib.RM_E_INVAL
+    assert lib.rm_mixed_replay(None) == _lib.RM_E_INVAL
+    assert lib.rm_mixed_set_stream(None, None) == _lib.RM_E_INVAL
+    assert lib.rm_mixed_set_grid(None, 0, 0) == _lib.RM_E_INVAL
+    lib.rm_mixed_destroy(None)  # NULL-safe
+    assert rmd.rm_mixed_create(0) == 0
+    assert "max_tiles" in rmd.rm_last_error()
+
+
+def test_mixed_create_without_device_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    assert rmd.rm_mixed_create(1024) == 0
+    assert "HIP" in rmd.rm_last_error()
