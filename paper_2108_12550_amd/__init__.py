@@ -49,9 +49,9 @@ class Decoder:
         self.N = 1 << m
         self.K = code_dimension(m, r)
 
-    def close(self):
+    def close(self, _destroy=rm_decoder_destroy):
         if getattr(self, "_h", 0):
-            rm_decoder_destroy(self._h)
+            _destroy(self._h)
             self._h = 0
 
     def __del__(self):
@@ -156,9 +156,9 @@ class MixedLauncher:
         return {"waves_per_block": t.waves_per_block, "blocks": t.blocks,
                 "tile_frames": [t.tile_frames[i] for i in range(len(segments))], "ms": t.ms, "trials": t.trials}
 
-    def close(self):
+    def close(self, _destroy=rm_mixed_destroy):
         if getattr(self, "_h", 0):
-            rm_mixed_destroy(self._h)
+            _destroy(self._h)
             self._h = 0
         self._held = None
 

@@ -948,17 +948,17 @@ __device__ __forceinline__ RootRes<M, R, L, D> decode_root(const Ctx<M, R, L, D>
 
 // ---------------------------------------------------------------------------
 // One frame: the P decoders of Alg. 5, then the winner back in channel order.
-// The calling wavefront owns the LDS slice at `slice`.
+// The calling wavefront owns the LDS slice at `slice`; `lane` is its lane id.
 // ---------------------------------------------------------------------------
 template <int M, int R, int L, int D>
-__device__ __forceinline__ void decode_frame(const KernelArgs &args, int64_t f, unsigned char *slice)
+__device__ __forceinline__ void decode_frame(const KernelArgs &args, int64_t f, unsigned char *slice, int lane)
 {
     using Sh = Shape<M, R, L, D>;
     constexpr int N = Sh::N;
     constexpr int G = Sh::G;
     Ctx<M, R, L, D> c;
     c.base = slice;
-    c.lane = lane_id();
+    c.lane = lane;
     {
         const int gw = c.lane / G;
         c.g = gw % L;
@@ -1065,10 +1065,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
 {
     using Sh = Shape<M, R, L, D>;
     const int wave = (int)(threadIdx.x / kWave);
-    unsigned char *slice = rm_smem + wave * Sh::BYTES;
     const int64_t stride = (int64_t)gridDim.x * args.waves;
-    for (int64_t f = (int64_t)blockIdx.x * args.waves + wave; f < args.n_frames; f += stride)
-        decode_frame<M, R, L, D>(args, f, slice);
+    for (int64_t f = (int64_t)blockIdx.x * args.waves + wave; f < args.n_frames; f += stride) {
+        uint32_t tid; // opaque per frame: see rm_mixed_kernel
+        asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"(threadIdx.x));
+        decode_frame<M, R, L, D>(args, f, rm_smem + (tid / kWave) * Sh::BYTES, (int)(tid & (kWave - 1)));
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1118,17 +1120,15 @@ struct MaxBytes {
 };
 
 template <class C>
-__device__ __forceinline__ void run_tile(const KernelArgs &a, const Tile &t, unsigned char *slice)
+__device__ __forceinline__ void run_tile(const KernelArgs &a, const Tile &t, unsigned char *slice, int lane)
 {
     for (uint32_t k = 0; k < t.count; k++)
-        decode_frame<C::M, C::R, C::L, C::D>(a, (int64_t)t.first + k, slice);
+        decode_frame<C::M, C::R, C::L, C::D>(a, (int64_t)t.first + k, slice, lane);
 }
 
 template <int WPE, class... Codes>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) rm_mixed_kernel(MixedArgs a)
 {
-    const int wave = (int)(threadIdx.x / kWave);
-    unsigned char *slice = rm_smem + wave * MaxBytes<Codes...>::value;
     while (true) {
         uint32_t t = 0;
         if (lane_id() == 0)
@@ -1136,11 +1136,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
         t = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
         if (t >= a.n_tiles)
             break; // every wave ends once the queue is drained
+        // The thread id is re-read through an opaque move on every tile, so
+        // that values derived from it stay inside each code's branch instead
+        // of being hoisted out of the loop, where those of all codes would
+        // be live at once.
+        uint32_t tid;
+        asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"(threadIdx.x));
+        const int lane = (int)(tid & (kWave - 1));
+        unsigned char *slice = rm_smem + (tid / kWave) * MaxBytes<Codes...>::value;
         const Tile tile = a.tiles[t];
         const int code = a.code[tile.seg];
         const KernelArgs &ka = a.seg[tile.seg];
         int idx = 0;
-        ((code == idx++ ? (run_tile<Codes>(ka, tile, slice), 0) : 0), ...);
+        ((code == idx++ ? (run_tile<Codes>(ka, tile, slice, lane), 0) : 0), ...);
     }
 }
 
