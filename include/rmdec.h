@@ -38,6 +38,7 @@ extern "C" {
 #define RM_E_HIP (-3)         /* a HIP runtime call failed (message has details) */
 #define RM_E_UNSUPPORTED (-4) /* no kernel built for this (m, r, L, mode)        */
 #define RM_E_PTR (-5)         /* a host pointer was passed where device memory is required */
+/* RM_E_AGAIN (-6) is defined with the request server below */
 
 /* Permutation mode. */
 #define RM_PERM_NONE 0 /* FHT-FSCL: identity, no permutation domain (needs L = 1) */
@@ -206,6 +207,110 @@ int rm_mixed_autotune(rm_mixed *mx, const rm_segment *segs, int n_segs, int reps
 
 /* Release after the work queued on its stream completes.  NULL-safe. */
 void rm_mixed_destroy(rm_mixed *mx);
+
+/*
+ * Request server: continuous batching of single-frame requests of any code,
+ * P and L that a serving kernel is built for (rm_server_supported).
+ *
+ * Each admitted request is copied into the open batch (its LLRs into the
+ * batch's pinned staging area, or, for device-resident LLRs, only its
+ * address).  The open batch is launched as soon as fewer than `depth`
+ * batches are on the device; until then it keeps admitting requests, so
+ * batches grow with the load.  A launch is one upload, one persistent
+ * kernel per list size present (each frame decoded exactly as by
+ * rm_decode_batch with the request's decoder: Alg. 5 over Alg. 2-4 and the
+ * SPC rules) and one download; up to `depth` batches run concurrently on
+ * their own streams.  Admission is by memory footprint: a request is
+ * refused with RM_E_AGAIN when the open batch has no room for its LLRs
+ * (4N bytes of `batch_bytes`), no free request slot, or when no batch
+ * buffer is free to open; it can be submitted again after rm_server_poll
+ * has retired finished batches.  All device and pinned memory is allocated
+ * at create: (depth + 1) batch buffers.
+ *
+ * Results are identical to decoding the same frame alone with
+ * rm_decode_batch (they do not depend on batch composition).  Not
+ * thread-safe: one host thread at a time per server.
+ */
+#define RM_E_AGAIN (-6) /* not admitted now: retry after rm_server_poll */
+
+typedef struct rm_server rm_server;
+
+typedef struct rm_server_config {
+    int64_t batch_bytes;    /* LLR bytes one batch can hold (>= 4096)                   */
+    int max_batch;          /* requests per batch, 1..65536                             */
+    int depth;              /* batches on the device at once, 1..4                      */
+    int tile_frames;        /* requests per queue entry of a kernel, 1..64 (0 = 2)      */
+} rm_server_config;
+
+typedef struct rm_request {
+    const rm_decoder *dec;  /* decoder of the request (code, P, L, tables)              */
+    const float *llr;       /* the frame's N float32 LLRs                               */
+    int llr_on_device;      /* 0: host memory, copied at submit; 1: device memory that
+                               must stay valid until the request completes            */
+    uint64_t tag;           /* caller's value, returned in the completion               */
+    double t_arrival_us;    /* arrival time on rm_server_now_us()'s clock; 0 = now      */
+    uint8_t *out_bits;      /* optional host destination of the N/8 codeword bytes     */
+    float *out_metric;      /* optional host destination of the final metric           */
+} rm_request;
+
+typedef struct rm_completion {
+    uint64_t ticket, tag;
+    int status;             /* RM_OK                                                    */
+    int n_bytes;            /* N/8                                                      */
+    float metric;           /* final path metric                                        */
+    uint8_t bits[128];      /* codeword, bit i at byte i>>3, bit i&7                    */
+    double t_arrival_us, t_launch_us, t_done_us; /* rm_server_now_us() clock           */
+} rm_completion;
+
+/* Create a server on the current device.  NULL on error (rm_last_error()). */
+rm_server *rm_server_create(const rm_server_config *cfg);
+
+/* 1 if requests of (m, r, L) can be served, else 0.  Host only. */
+int rm_server_supported(int m, int r, int L);
+
+/* Microseconds on the server's monotonic clock. */
+double rm_server_now_us(void);
+
+/*
+ * Declare device memory [base, base + bytes) that device-resident requests
+ * (llr_on_device = 1) may point into; checked once here (RM_E_PTR if it is
+ * not device memory), so that submit only checks ranges.  Up to 16 pools.
+ */
+int rm_server_register_pool(rm_server *s, const void *base, int64_t bytes);
+
+/*
+ * Admit one request: RM_OK and *ticket set (tickets count up from 1), or
+ * RM_E_AGAIN (not admitted: nothing kept), RM_E_UNSUPPORTED (no serving
+ * kernel for its code and L), RM_E_PTR (device-resident LLRs outside every
+ * registered pool), RM_E_INVAL.  May launch the open batch.
+ */
+int rm_server_submit(rm_server *s, const rm_request *req, uint64_t *ticket);
+
+/*
+ * Non-blocking progress: retire finished batches, write up to `max`
+ * completions (oldest batch first) and launch the open batch if a device
+ * slot is free.  Returns the number of completions written (>= 0) or an
+ * error code.  Completions not written stay queued for the next call.
+ */
+int rm_server_poll(rm_server *s, rm_completion *out, int max);
+
+/* Admitted requests whose completion has not yet been returned by poll. */
+int64_t rm_server_pending(const rm_server *s);
+
+/*
+ * Open-loop trace replay (load generator, runs on the calling thread):
+ * request i is submitted at t0 + arrival_us[i] (t0 = call time; arrival
+ * times non-decreasing), or as soon after as it is admitted; the call polls
+ * until every request has completed and writes latency_us[i] = completion
+ * time - (t0 + arrival_us[i]).  Requests' t_arrival_us fields are ignored.
+ * stats (may be NULL) receives: [0] elapsed us, [1] batches launched,
+ * [2] refused submit attempts, [3] largest batch.
+ */
+int rm_server_run_trace(rm_server *s, const rm_request *reqs, const double *arrival_us, int64_t n,
+                        double *latency_us, double *stats);
+
+/* Release after all device work completes; pending completions are dropped.  NULL-safe. */
+void rm_server_destroy(rm_server *s);
 
 #ifdef __cplusplus
 }

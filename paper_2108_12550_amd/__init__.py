@@ -8,22 +8,28 @@ memory and streams only.
 """
 from __future__ import annotations
 
+import ctypes
 from math import comb
 
 from . import _lib
-from ._lib import (RM_E_HIP, RM_E_INVAL, RM_E_NOMEM, RM_E_PTR, RM_E_UNSUPPORTED, RM_MIXED_MAX_SEGMENTS, RM_OK,
-                   RM_PERM_NONE, RM_PERM_PFHT, rm_config, rm_decode_batch, rm_decoder_create, rm_decoder_create_ex,
-                   rm_decoder_destroy, rm_decoder_info, rm_decoder_set_stream, rm_last_error, rm_mixed_autotune,
-                   rm_mixed_capture, rm_mixed_create, rm_mixed_decode, rm_mixed_destroy, rm_mixed_replay,
-                   rm_mixed_set_grid, rm_mixed_set_stream, rm_mixed_supported, rm_mixed_tuning, rm_perm_tables,
-                   rm_segment, rm_supported)
+from ._lib import (RM_E_AGAIN, RM_E_HIP, RM_E_INVAL, RM_E_NOMEM, RM_E_PTR, RM_E_UNSUPPORTED, RM_MIXED_MAX_SEGMENTS,
+                   RM_OK, RM_PERM_NONE, RM_PERM_PFHT, rm_completion, rm_config, rm_decode_batch, rm_decoder_create,
+                   rm_decoder_create_ex, rm_decoder_destroy, rm_decoder_info, rm_decoder_set_stream, rm_last_error,
+                   rm_mixed_autotune, rm_mixed_capture, rm_mixed_create, rm_mixed_decode, rm_mixed_destroy,
+                   rm_mixed_replay, rm_mixed_set_grid, rm_mixed_set_stream, rm_mixed_supported, rm_mixed_tuning,
+                   rm_perm_tables, rm_request, rm_segment, rm_server_config, rm_server_create, rm_server_destroy,
+                   rm_server_now_us, rm_server_pending, rm_server_poll, rm_server_register_pool, rm_server_run_trace,
+                   rm_server_submit, rm_server_supported, rm_supported)
 
 __all__ = ["Decoder", "MixedLauncher", "perm_tables", "code_dimension", "RM_PERM_NONE", "RM_PERM_PFHT",
            "RM_MIXED_MAX_SEGMENTS", "rm_config", "rm_segment", "rm_decode_batch", "rm_decoder_create",
            "rm_decoder_create_ex", "rm_decoder_destroy", "rm_decoder_info", "rm_decoder_set_stream",
            "rm_last_error", "rm_perm_tables", "rm_supported", "rm_mixed_create", "rm_mixed_supported",
            "rm_mixed_set_stream", "rm_mixed_set_grid", "rm_mixed_decode", "rm_mixed_capture",
-           "rm_mixed_replay", "rm_mixed_autotune", "rm_mixed_tuning", "rm_mixed_destroy"]
+           "rm_mixed_replay", "rm_mixed_autotune", "rm_mixed_tuning", "rm_mixed_destroy", "Server",
+           "RM_E_AGAIN", "rm_server_config", "rm_request", "rm_completion", "rm_server_create",
+           "rm_server_supported", "rm_server_now_us", "rm_server_register_pool", "rm_server_submit",
+           "rm_server_poll", "rm_server_pending", "rm_server_run_trace", "rm_server_destroy"]
 
 
 def code_dimension(m: int, r: int) -> int:
@@ -161,6 +167,86 @@ class MixedLauncher:
             _destroy(self._h)
             self._h = 0
         self._held = None
+
+    def __del__(self):
+        self.close()
+
+
+class Server:
+    """Request server (rm_server_* of the C ABI): continuous batching of
+    single-frame requests of any served code, P and L."""
+
+    def __init__(self, batch_bytes: int = 64 << 20, max_batch: int = 16384, depth: int = 2, tile_frames: int = 0):
+        self._h = rm_server_create(rm_server_config(batch_bytes, max_batch, depth, tile_frames))
+        if not self._h:
+            raise RMError(-1, rm_last_error())
+        self._keep = []  # device pools and decoders the requests refer to
+        self._cbuf = (rm_completion * 4096)()
+
+    @staticmethod
+    def supported(m: int, r: int, L: int) -> bool:
+        return rm_server_supported(m, r, L)
+
+    @staticmethod
+    def now_us() -> float:
+        return rm_server_now_us()
+
+    def register_pool(self, tensor):
+        """Allow device-resident requests to point into this CUDA tensor."""
+        rc = rm_server_register_pool(self._h, tensor.data_ptr(), tensor.numel() * tensor.element_size())
+        if rc != RM_OK:
+            raise RMError(rc, rm_last_error())
+        self._keep.append(tensor)
+
+    def submit(self, dec: "Decoder", llr_ptr: int, on_device: bool, tag: int = 0, t_arrival_us: float = 0.0):
+        """Returns the ticket, or None if not admitted now (RM_E_AGAIN)."""
+        rc, t = rm_server_submit(self._h, rm_request(dec._h, llr_ptr, int(on_device), tag, t_arrival_us, None, None))
+        if rc == RM_E_AGAIN:
+            return None
+        if rc != RM_OK:
+            raise RMError(rc, rm_last_error())
+        return t
+
+    def poll(self, max_n: int = 4096):
+        """Completions now available: list of (ticket, tag, bits bytes, metric, t_arrival, t_launch, t_done)."""
+        k = rm_server_poll(self._h, self._cbuf, min(max_n, len(self._cbuf)))
+        if k < 0:
+            raise RMError(k, rm_last_error())
+        return [(c.ticket, c.tag, bytes(c.bits[:c.n_bytes]), c.metric, c.t_arrival_us, c.t_launch_us, c.t_done_us)
+                for c in self._cbuf[:k]]
+
+    def pending(self) -> int:
+        return rm_server_pending(self._h)
+
+    def run_trace(self, requests, arrival_us, out_bits=None, out_metric=None):
+        """Open-loop replay; requests = list of (decoder, llr_ptr, on_device).
+        Optional numpy outputs: out_bits (n, 128) uint8, out_metric (n,)
+        float32.  Returns (latency_us ndarray, stats dict)."""
+        import numpy as np
+        n = len(requests)
+        reqs = (rm_request * max(1, n))()
+        ob = out_bits.ctypes.data if out_bits is not None else 0
+        om = out_metric.ctypes.data if out_metric is not None else 0
+        if out_bits is not None:
+            assert out_bits.dtype == np.uint8 and out_bits.shape == (n, 128) and out_bits.flags.c_contiguous
+        if out_metric is not None:
+            assert out_metric.dtype == np.float32 and out_metric.shape == (n,) and out_metric.flags.c_contiguous
+        for i, (dec, ptr, dev) in enumerate(requests):
+            reqs[i] = rm_request(dec._h, ptr, int(dev), i, 0.0, ob + 128 * i if ob else None, om + 4 * i if om else None)
+        arr = np.ascontiguousarray(arrival_us, dtype=np.float64)
+        lat = np.zeros(n, dtype=np.float64)
+        st = np.zeros(4, dtype=np.float64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        rc = rm_server_run_trace(self._h, reqs, arr.ctypes.data_as(dp), n, lat.ctypes.data_as(dp),
+                                 st.ctypes.data_as(dp))
+        if rc != RM_OK:
+            raise RMError(rc, rm_last_error())
+        return lat, {"elapsed_us": st[0], "batches": int(st[1]), "refused": int(st[2]), "largest_batch": int(st[3])}
+
+    def close(self, _destroy=rm_server_destroy):
+        if getattr(self, "_h", 0):
+            _destroy(self._h)
+            self._h = 0
 
     def __del__(self):
         self.close()

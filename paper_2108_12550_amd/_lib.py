@@ -17,6 +17,7 @@ RM_E_NOMEM = -2
 RM_E_HIP = -3
 RM_E_UNSUPPORTED = -4
 RM_E_PTR = -5
+RM_E_AGAIN = -6
 
 RM_PERM_NONE = 0
 RM_PERM_PFHT = 1
@@ -24,7 +25,9 @@ RM_PERM_PFHT = 1
 EXPORTED = ("rm_decoder_create", "rm_decoder_create_ex", "rm_decode_batch", "rm_decoder_destroy",
             "rm_decoder_set_stream", "rm_decoder_info", "rm_perm_tables", "rm_supported", "rm_last_error",
             "rm_mixed_create", "rm_mixed_supported", "rm_mixed_set_stream", "rm_mixed_set_grid", "rm_mixed_decode",
-            "rm_mixed_capture", "rm_mixed_replay", "rm_mixed_autotune", "rm_mixed_destroy")
+            "rm_mixed_capture", "rm_mixed_replay", "rm_mixed_autotune", "rm_mixed_destroy",
+            "rm_server_create", "rm_server_supported", "rm_server_now_us", "rm_server_register_pool",
+            "rm_server_submit", "rm_server_poll", "rm_server_pending", "rm_server_run_trace", "rm_server_destroy")
 
 RM_MIXED_MAX_SEGMENTS = 8
 
@@ -51,6 +54,23 @@ class rm_mixed_tuning(ctypes.Structure):
     _fields_ = [("blocks", ctypes.c_int), ("waves_per_block", ctypes.c_int),
                 ("tile_frames", ctypes.c_int * RM_MIXED_MAX_SEGMENTS), ("ms", ctypes.c_float),
                 ("trials", ctypes.c_int)]
+
+
+class rm_server_config(ctypes.Structure):
+    _fields_ = [("batch_bytes", ctypes.c_int64), ("max_batch", ctypes.c_int), ("depth", ctypes.c_int),
+                ("tile_frames", ctypes.c_int)]
+
+
+class rm_request(ctypes.Structure):
+    _fields_ = [("dec", ctypes.c_void_p), ("llr", ctypes.c_void_p), ("llr_on_device", ctypes.c_int),
+                ("tag", ctypes.c_uint64), ("t_arrival_us", ctypes.c_double), ("out_bits", ctypes.c_void_p),
+                ("out_metric", ctypes.c_void_p)]
+
+
+class rm_completion(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("tag", ctypes.c_uint64), ("status", ctypes.c_int),
+                ("n_bytes", ctypes.c_int), ("metric", ctypes.c_float), ("bits", ctypes.c_uint8 * 128),
+                ("t_arrival_us", ctypes.c_double), ("t_launch_us", ctypes.c_double), ("t_done_us", ctypes.c_double)]
 
 
 _lib = None
@@ -101,6 +121,25 @@ def load() -> ctypes.CDLL:
     L.rm_mixed_replay.argtypes = [vp]
     L.rm_mixed_autotune.restype = ctypes.c_int
     L.rm_mixed_autotune.argtypes = [vp, P(rm_segment), ctypes.c_int, ctypes.c_int, P(rm_mixed_tuning)]
+    L.rm_server_create.restype = vp
+    L.rm_server_create.argtypes = [P(rm_server_config)]
+    L.rm_server_supported.restype = ctypes.c_int
+    L.rm_server_supported.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.rm_server_now_us.restype = ctypes.c_double
+    L.rm_server_now_us.argtypes = []
+    L.rm_server_register_pool.restype = ctypes.c_int
+    L.rm_server_register_pool.argtypes = [vp, vp, ctypes.c_int64]
+    L.rm_server_submit.restype = ctypes.c_int
+    L.rm_server_submit.argtypes = [vp, P(rm_request), P(ctypes.c_uint64)]
+    L.rm_server_poll.restype = ctypes.c_int
+    L.rm_server_poll.argtypes = [vp, P(rm_completion), ctypes.c_int]
+    L.rm_server_pending.restype = ctypes.c_int64
+    L.rm_server_pending.argtypes = [vp]
+    L.rm_server_run_trace.restype = ctypes.c_int
+    L.rm_server_run_trace.argtypes = [vp, P(rm_request), P(ctypes.c_double), ctypes.c_int64, P(ctypes.c_double),
+                                      P(ctypes.c_double)]
+    L.rm_server_destroy.restype = None
+    L.rm_server_destroy.argtypes = [vp]
     L.rm_mixed_destroy.restype = None
     L.rm_mixed_destroy.argtypes = [vp]
     _lib = L
@@ -194,3 +233,41 @@ def rm_mixed_autotune(mx: int, segs, reps: int):
 
 def rm_mixed_destroy(mx: int) -> None:
     load().rm_mixed_destroy(mx)
+
+
+def rm_server_create(cfg: rm_server_config) -> int:
+    return load().rm_server_create(ctypes.byref(cfg)) or 0
+
+
+def rm_server_supported(m: int, r: int, L: int) -> bool:
+    return bool(load().rm_server_supported(m, r, L))
+
+
+def rm_server_now_us() -> float:
+    return load().rm_server_now_us()
+
+
+def rm_server_register_pool(srv: int, base: int, nbytes: int) -> int:
+    return load().rm_server_register_pool(srv, base, nbytes)
+
+
+def rm_server_submit(srv: int, req: rm_request):
+    t = ctypes.c_uint64(0)
+    rc = load().rm_server_submit(srv, ctypes.byref(req), ctypes.byref(t))
+    return rc, t.value
+
+
+def rm_server_poll(srv: int, out, max_n: int) -> int:
+    return load().rm_server_poll(srv, out, max_n)
+
+
+def rm_server_pending(srv: int) -> int:
+    return load().rm_server_pending(srv)
+
+
+def rm_server_run_trace(srv: int, reqs, arrival_us, n: int, latency_us, stats) -> int:
+    return load().rm_server_run_trace(srv, reqs, arrival_us, n, latency_us, stats)
+
+
+def rm_server_destroy(srv: int) -> None:
+    load().rm_server_destroy(srv)

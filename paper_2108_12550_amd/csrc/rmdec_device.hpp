@@ -948,10 +948,14 @@ __device__ __forceinline__ RootRes<M, R, L, D> decode_root(const Ctx<M, R, L, D>
 
 // ---------------------------------------------------------------------------
 // One frame: the P decoders of Alg. 5, then the winner back in channel order.
-// The calling wavefront owns the LDS slice at `slice`; `lane` is its lane id.
+// The frame's N channel LLRs are read from `src`; the codeword goes to `ob`
+// (N/8 bytes) and the final metric to `opm` (if not null).  The calling
+// wavefront owns the LDS slice at `slice`; `lane` is its lane id.  From
+// `args` only the decoder set (maps, P, mode) is used.
 // ---------------------------------------------------------------------------
 template <int M, int R, int L, int D>
-__device__ __forceinline__ void decode_frame(const KernelArgs &args, int64_t f, unsigned char *slice, int lane)
+__device__ __forceinline__ void decode_frame(const KernelArgs &args, const float *src, uint8_t *ob, float *opm,
+                                             unsigned char *slice, int lane)
 {
     using Sh = Shape<M, R, L, D>;
     constexpr int N = Sh::N;
@@ -967,7 +971,6 @@ __device__ __forceinline__ void decode_frame(const KernelArgs &args, int64_t f, 
         c.lg = c.lane % G;
     }
     c.pfht = args.pfht;
-    const float *src = args.llr + f * N;
     wave_sync();
     for (int i = c.lane; i < N; i += kWave)
         c.y()[i] = src[i];
@@ -1023,7 +1026,6 @@ __device__ __forceinline__ void decode_frame(const KernelArgs &args, int64_t f, 
     for (int k = 0; k < M; k++)
         col[k] = mi[k];
     col[M] = mi[kMapB];
-    uint8_t *ob = args.out_bits + f * (N / 8);
 #pragma unroll
     for (int j0 = 0; j0 < N; j0 += kWave) {
         const uint32_t j = (uint32_t)(j0 + c.lane);
@@ -1052,9 +1054,18 @@ __device__ __forceinline__ void decode_frame(const KernelArgs &args, int64_t f, 
                 ob[c.lane] = (uint8_t)(mask >> (8 * c.lane));
         }
     }
-    if (args.out_pm && c.lane == 0)
-        args.out_pm[f] = best;
+    if (opm && c.lane == 0)
+        *opm = best;
     wave_sync();
+}
+
+// frame f of a contiguous batch
+template <int M, int R, int L, int D>
+__device__ __forceinline__ void decode_batch_frame(const KernelArgs &args, int64_t f, unsigned char *slice, int lane)
+{
+    constexpr int N = 1 << M;
+    decode_frame<M, R, L, D>(args, args.llr + f * N, args.out_bits + f * (N / 8), args.out_pm ? args.out_pm + f : nullptr,
+                             slice, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -1069,7 +1080,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
     for (int64_t f = (int64_t)blockIdx.x * args.waves + wave; f < args.n_frames; f += stride) {
         uint32_t tid; // opaque per frame: see rm_mixed_kernel
         asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"(threadIdx.x));
-        decode_frame<M, R, L, D>(args, f, rm_smem + (tid / kWave) * Sh::BYTES, (int)(tid & (kWave - 1)));
+        decode_batch_frame<M, R, L, D>(args, f, rm_smem + (tid / kWave) * Sh::BYTES, (int)(tid & (kWave - 1)));
     }
 }
 
@@ -1123,7 +1134,7 @@ template <class C>
 __device__ __forceinline__ void run_tile(const KernelArgs &a, const Tile &t, unsigned char *slice, int lane)
 {
     for (uint32_t k = 0; k < t.count; k++)
-        decode_frame<C::M, C::R, C::L, C::D>(a, (int64_t)t.first + k, slice, lane);
+        decode_batch_frame<C::M, C::R, C::L, C::D>(a, (int64_t)t.first + k, slice, lane);
 }
 
 template <int WPE, class... Codes>
@@ -1149,6 +1160,67 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
         const KernelArgs &ka = a.seg[tile.seg];
         int idx = 0;
         ((code == idx++ ? (run_tile<Codes>(ka, tile, slice, lane), 0) : 0), ...);
+    }
+}
+
+} // namespace rmdec
+
+namespace rmdec {
+
+// ---------------------------------------------------------------------------
+// Serving launch: like the fused kernel, but every frame is a separate
+// request with its own input address and output slot, and the decoder sets
+// of a step are a table in device memory.
+// ---------------------------------------------------------------------------
+struct Job {
+    const float *llr; // the request's N channel LLRs (device)
+    uint32_t out;     // output slot: bits at out * kServeBitsStride, metric at out
+    uint32_t pad;
+};
+
+constexpr int kServeBitsStride = 128; // bytes per output slot (N/8 <= 128)
+
+struct ServeArgs {
+    const KernelArgs *segs; // per decoder set of the step: maps, P, mode (llr/out fields unused)
+    const int *seg_code;    // index of each set's code in the kernel's code list
+    const Tile *tiles;      // runs of jobs of one set: seg, first job, count
+    const Job *jobs;
+    uint32_t n_tiles;
+    uint32_t *head; // next tile to take; zero when the step starts
+    uint8_t *out_bits;
+    float *out_pm;
+};
+
+template <class C>
+__device__ __forceinline__ void serve_tile(const ServeArgs &a, const KernelArgs &ka, const Tile &t, unsigned char *slice,
+                                           int lane)
+{
+    for (uint32_t k = 0; k < t.count; k++) {
+        const Job j = a.jobs[t.first + k];
+        decode_frame<C::M, C::R, C::L, C::D>(ka, j.llr, a.out_bits + (size_t)j.out * kServeBitsStride, a.out_pm + j.out,
+                                             slice, lane);
+    }
+}
+
+template <int WPE, class... Codes>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) rm_serve_kernel(ServeArgs a)
+{
+    while (true) {
+        uint32_t t = 0;
+        if (lane_id() == 0)
+            t = atomicAdd(a.head, 1u);
+        t = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
+        if (t >= a.n_tiles)
+            break; // every wave ends once the step's queue is drained
+        uint32_t tid; // opaque per tile: see rm_mixed_kernel
+        asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"(threadIdx.x));
+        const int lane = (int)(tid & (kWave - 1));
+        unsigned char *slice = rm_smem + (tid / kWave) * MaxBytes<Codes...>::value;
+        const Tile tile = a.tiles[t];
+        const int code = a.seg_code[tile.seg];
+        const KernelArgs ka = a.segs[tile.seg];
+        int idx = 0;
+        ((code == idx++ ? (serve_tile<Codes>(a, ka, tile, slice, lane), 0) : 0), ...);
     }
 }
 

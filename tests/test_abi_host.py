@@ -119,3 +119,33 @@ def test_mixed_create_without_device_fails_cleanly():
         pytest.skip("a GPU is present")
     assert rmd.rm_mixed_create(1024) == 0
     assert "HIP" in rmd.rm_last_error()
+
+
+def test_server_codes_and_lists():
+    for m, r in ((7, 2), (8, 2), (9, 2), (10, 2), (8, 3)):
+        for L in (1, 4, 8):
+            assert rmd.rm_server_supported(m, r, L)
+    assert not rmd.rm_server_supported(9, 2, 2)
+    assert not rmd.rm_server_supported(6, 3, 4)
+
+
+def test_server_null_and_invalid_calls():
+    lib = _lib.load()
+    assert lib.rm_server_submit(None, None, None) == _lib.RM_E_INVAL
+    assert lib.rm_server_poll(None, None, 0) == _lib.RM_E_INVAL
+    assert lib.rm_server_register_pool(None, None, 0) == _lib.RM_E_INVAL
+    assert lib.rm_server_pending(None) == 0
+    lib.rm_server_destroy(None)  # NULL-safe
+    for cfg in ((1024, 16, 2, 0), (1 << 20, 0, 2, 0), (1 << 20, 16, 5, 0), (1 << 20, 16, 2, 65)):
+        assert rmd.rm_server_create(rmd.rm_server_config(*cfg)) == 0
+        assert "config" in rmd.rm_last_error()
+    a, b = rmd.rm_server_now_us(), rmd.rm_server_now_us()
+    assert 0 < a <= b
+
+
+def test_server_create_without_device_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    assert rmd.rm_server_create(rmd.rm_server_config(1 << 20, 64, 2, 0)) == 0
+    assert "HIP" in rmd.rm_last_error()
