@@ -223,22 +223,36 @@ class Server:
         Optional numpy outputs: out_bits (n, 128) uint8, out_metric (n,)
         float32.  Returns (latency_us ndarray, stats dict)."""
         import numpy as np
-        n = len(requests)
-        reqs = (rm_request * max(1, n))()
-        ob = out_bits.ctypes.data if out_bits is not None else 0
-        om = out_metric.ctypes.data if out_metric is not None else 0
+        handles = np.array([d._h for d, _, _ in requests], dtype=np.uint64)
+        ptrs = np.array([p for _, p, _ in requests], dtype=np.uint64)
+        dev = np.array([int(v) for _, _, v in requests], dtype=np.int32)
+        return self.run_trace_arrays(handles, ptrs, dev, arrival_us, out_bits, out_metric)
+
+    def run_trace_arrays(self, dec_handles, llr_ptrs, on_device, arrival_us, out_bits=None, out_metric=None):
+        """run_trace with the requests given as arrays: decoder handles
+        (Decoder._h), LLR addresses and on-device flags."""
+        import numpy as np
+        n = len(arrival_us)
+        f = {name: getattr(rm_request, name).offset for name, _ in rm_request._fields_}
+        dt = np.dtype({"names": list(f), "offsets": list(f.values()), "itemsize": ctypes.sizeof(rm_request),
+                       "formats": ["u8", "u8", "i4", "u8", "f8", "u8", "u8"]})
+        reqs = np.zeros(max(1, n), dtype=dt)
+        reqs["dec"][:n] = dec_handles
+        reqs["llr"][:n] = llr_ptrs
+        reqs["llr_on_device"][:n] = on_device
+        reqs["tag"][:n] = np.arange(n, dtype=np.uint64)
         if out_bits is not None:
             assert out_bits.dtype == np.uint8 and out_bits.shape == (n, 128) and out_bits.flags.c_contiguous
+            reqs["out_bits"][:n] = out_bits.ctypes.data + 128 * np.arange(n, dtype=np.uint64)
         if out_metric is not None:
             assert out_metric.dtype == np.float32 and out_metric.shape == (n,) and out_metric.flags.c_contiguous
-        for i, (dec, ptr, dev) in enumerate(requests):
-            reqs[i] = rm_request(dec._h, ptr, int(dev), i, 0.0, ob + 128 * i if ob else None, om + 4 * i if om else None)
+            reqs["out_metric"][:n] = out_metric.ctypes.data + 4 * np.arange(n, dtype=np.uint64)
         arr = np.ascontiguousarray(arrival_us, dtype=np.float64)
         lat = np.zeros(n, dtype=np.float64)
         st = np.zeros(4, dtype=np.float64)
         dp = ctypes.POINTER(ctypes.c_double)
-        rc = rm_server_run_trace(self._h, reqs, arr.ctypes.data_as(dp), n, lat.ctypes.data_as(dp),
-                                 st.ctypes.data_as(dp))
+        rc = rm_server_run_trace(self._h, reqs.ctypes.data_as(ctypes.POINTER(rm_request)), arr.ctypes.data_as(dp), n,
+                                 lat.ctypes.data_as(dp), st.ctypes.data_as(dp))
         if rc != RM_OK:
             raise RMError(rc, rm_last_error())
         return lat, {"elapsed_us": st[0], "batches": int(st[1]), "refused": int(st[2]), "largest_batch": int(st[3])}

@@ -53,7 +53,9 @@ struct ReqMeta {
 // LLRs and outputs of up to max_batch requests.
 struct Batch {
     enum State { FREE, OPEN, INFLIGHT, DONE } state = FREE;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;          // upload, list-size-1 kernel, download
+    hipStream_t side[2] = {nullptr, nullptr}; // list-size-4 and -8 kernels, concurrent with the first
+    hipEvent_t uploaded = nullptr, side_done[2] = {nullptr, nullptr};
     hipEvent_t done = nullptr;
     unsigned char *h_tab = nullptr, *d_tab = nullptr; // heads | segs | codes | jobs | tiles
     unsigned char *h_llr = nullptr, *d_llr = nullptr;
@@ -93,10 +95,12 @@ void free_batch(Batch &b)
 {
     if (b.stream)
         (void)hipStreamSynchronize(b.stream);
-    if (b.done)
-        (void)hipEventDestroy(b.done);
-    if (b.stream)
-        (void)hipStreamDestroy(b.stream);
+    for (hipEvent_t ev : {b.done, b.uploaded, b.side_done[0], b.side_done[1]})
+        if (ev)
+            (void)hipEventDestroy(ev);
+    for (hipStream_t st : {b.stream, b.side[0], b.side[1]})
+        if (st)
+            (void)hipStreamDestroy(st);
     for (unsigned char *p : {b.h_tab, b.h_llr, b.h_out})
         if (p)
             (void)hipHostFree(p);
@@ -109,8 +113,11 @@ hipError_t alloc_batch(rm_server *s, Batch &b)
 {
     const size_t out_bytes = s->out_pm_off + (size_t)s->cfg.max_batch * 4;
     hipError_t e = hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking);
-    if (e == hipSuccess)
-        e = hipEventCreateWithFlags(&b.done, hipEventDisableTiming);
+    for (int i = 0; i < 2 && e == hipSuccess; i++)
+        e = hipStreamCreateWithFlags(&b.side[i], hipStreamNonBlocking);
+    for (hipEvent_t *ev : {&b.done, &b.uploaded, &b.side_done[0], &b.side_done[1]})
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
     if (e == hipSuccess)
         e = hipHostMalloc((void **)&b.h_tab, s->tab_bytes, hipHostMallocDefault);
     if (e == hipSuccess)
@@ -148,7 +155,7 @@ bool open_batch(rm_server *s)
 }
 
 // Upload the open batch, launch one serving kernel per list size present
-// and queue the download; the batch then runs on its own stream.
+// (concurrently, on the batch's three streams) and queue the download.
 int launch_open(rm_server *s)
 {
     Batch &b = s->batches[s->open];
@@ -204,9 +211,17 @@ int launch_open(rm_server *s)
     hipError_t e = hipMemcpyAsync(b.d_tab, b.h_tab, tab_used, hipMemcpyHostToDevice, b.stream);
     if (e == hipSuccess && b.llr_used > 0)
         e = hipMemcpyAsync(b.d_llr, b.h_llr, (size_t)b.llr_used, hipMemcpyHostToDevice, b.stream);
-    for (int g = 0; e == hipSuccess && g < kGroups; g++) {
+    if (e == hipSuccess && (g_count[1] || g_count[2]))
+        e = hipEventRecord(b.uploaded, b.stream);
+    // the heaviest list size first
+    for (int g = kGroups - 1; e == hipSuccess && g >= 0; g--) {
         if (g_count[g] == 0)
             continue;
+        hipStream_t st = g == 0 ? b.stream : b.side[g - 1];
+        if (g > 0)
+            e = hipStreamWaitEvent(st, b.uploaded, 0);
+        if (e != hipSuccess)
+            break;
         ServeArgs a;
         a.segs = (const KernelArgs *)(b.d_tab + s->off_segs);
         a.seg_code = (const int *)(b.d_tab + s->off_codes);
@@ -217,8 +232,13 @@ int launch_open(rm_server *s)
         a.out_bits = b.d_out;
         a.out_pm = (float *)(b.d_out + s->out_pm_off);
         const int want = (g_count[g] + s->waves - 1) / s->waves;
-        e = group(g).launch(a, std::min(want, s->grid_max[g]), s->waves, b.stream);
+        e = group(g).launch(a, std::min(want, s->grid_max[g]), s->waves, st);
+        if (e == hipSuccess && g > 0)
+            e = hipEventRecord(b.side_done[g - 1], st);
     }
+    for (int g = 1; e == hipSuccess && g < kGroups; g++)
+        if (g_count[g])
+            e = hipStreamWaitEvent(b.stream, b.side_done[g - 1], 0);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b.h_out, b.d_out, (size_t)n * kServeBitsStride, hipMemcpyDeviceToHost, b.stream);
     if (e == hipSuccess)
