@@ -174,6 +174,10 @@ __device__ __forceinline__ uint64_t from_lane(uint64_t v, int src)
 {
     return ((uint64_t)from_lane((uint32_t)(v >> 32), src) << 32) | from_lane((uint32_t)v, src);
 }
+__device__ __forceinline__ double from_lane(double v, int src)
+{
+    return __longlong_as_double((long long)from_lane((uint64_t)__double_as_longlong(v), src));
+}
 
 // butterflies over aligned blocks of 2W lanes (W = 2^k or 0); every lane of
 // a block ends with the same value
@@ -354,6 +358,46 @@ __device__ __forceinline__ void select_smallest(const float *pm, int *slot, int 
     }
 }
 
+// 64-bit value held by lane (lane ^ W)
+template <int W>
+__device__ __forceinline__ double xor64(double v)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint64_t r = ((uint64_t)xor_any<W>((uint32_t)(u >> 32)) << 32) | xor_any<W>((uint32_t)u);
+    return __longlong_as_double((long long)r);
+}
+
+// Bitonic half-cleaners with strides S, S/2, ..., 1 over lanes: the lower
+// lane of each pair keeps the smaller key.  Sorts a bitonic sequence held in
+// 2S consecutive lanes.
+template <int S>
+__device__ __forceinline__ double bitonic_clean(double key, int lg)
+{
+    if constexpr (S == 0) {
+        return key;
+    } else {
+        const double o = xor64<S>(key);
+        const double lo = dmin(key, o), hi = dmax(key, o);
+        return bitonic_clean<S / 2>((lg & S) ? hi : lo, lg);
+    }
+}
+
+// Merge of L sorted lists of K keys (list g in lanes g*G + t, t < K, keys
+// ascending in t) into the K smallest, ascending, in the lanes of list 0.
+// Level LV merges list g with list g ^ 2^LV: the first list against the
+// second reversed gives the K smallest of both as a bitonic sequence, which
+// the half-cleaners sort.  Keys must be distinct, so the order is total.
+template <int LV, int L, int K, int G>
+__device__ __forceinline__ double merge_lists(double key, int lg)
+{
+    if constexpr ((1 << LV) >= L) {
+        return key;
+    } else {
+        const double o = xor64<(1 << LV) * G + (K - 1)>(key);
+        return merge_lists<LV + 1, L, K, G>(bitonic_clean<K / 2>(dmin(key, o), lg), lg);
+    }
+}
+
 // Byte addresses of elements p(i), i = lg + G j (j < RR), of a vector at
 // byte address `base` (aligned to the vector's size, so XOR acts as
 // addition), under an affine map on F2^MD stored in LDS as byte-scaled
@@ -427,12 +471,16 @@ __device__ __forceinline__ MaskT walsh_mask(uint32_t c)
     return w;
 }
 
-// FHT key: |F| widened to double, with (1024 - i, sign) in low mantissa bits
-// that the conversion leaves zero: a larger |F| wins, then the lower index.
+// FHT key: a 64-bit pattern with the bits of |F| as its high word and
+// ((1024 - i) << 1 | sign of F) as its low word.  Read as a double it is
+// positive and finite, and doubles of one sign order like their bit
+// patterns, so one v_max_f64 orders keys by |F| (larger first), then by the
+// index (lower first).  The low word is one funnel shift of (1024 - i, F).
 __device__ __forceinline__ double fht_key(float f, uint32_t i)
 {
-    const uint64_t d = (uint64_t)__double_as_longlong((double)fabsf(f));
-    return __longlong_as_double((long long)(d | (((1024u - i) << 1) | (f < 0.0f ? 1u : 0u))));
+    const uint32_t fb = __float_as_uint(f);
+    const uint32_t lo = __builtin_amdgcn_alignbit(1024u - i, fb, 31u);
+    return __longlong_as_double((long long)(((uint64_t)(fb & 0x7FFFFFFFu) << 32) | lo));
 }
 
 // ---------------------------------------------------------------------------
@@ -474,19 +522,14 @@ __device__ __forceinline__ NodeRes<(1 << S), kWave / (L * D)> fhtl(const Ctx<M, 
     }
     int left = 3; // keys of this lane known to be its largest below the last pop
 
-    // K rounds: the group's largest remaining key is the next candidate
-    float mypm = 0.0f;
-    uint32_t myinf = 0;
+    // K rounds: the group's largest remaining key is the next candidate;
+    // lane t of the group keeps the key of round t
+    double mykey = 0.0;
 #pragma unroll
     for (int t = 0; t < K; t++) {
         const double w = bfly_max<ACT / 2>(b1);
-        const uint64_t wb = (uint64_t)__double_as_longlong(w);
-        const float absf = (float)__longlong_as_double((long long)(wb & ~0x1FFFFFFFull));
-        const float cand = pm + 0.5f * (sabs - absf);
-        if (lg == t) {
-            mypm = cand;
-            myinf = (uint32_t)wb & 0xFFFu;
-        }
+        if (K == 1 || lg == t) // one round: every lane of the group holds the winner
+            mykey = w;
         if (t + 1 < K) {
             const bool own = valid && (b1 == w);
             if (own) {
@@ -519,24 +562,36 @@ __device__ __forceinline__ NodeRes<(1 << S), kWave / (L * D)> fhtl(const Ctx<M, 
         }
     }
 
-    // stable merge of the L*K candidates by metric, keep L (Alg. 3)
-    float *cpm = c.cpm();
-    uint32_t *cinf = c.cinf();
-    int *slot = c.slot();
-    if (lg < K) {
-        cpm[c.g * K + lg] = mypm;
-        cinf[c.g * K + lg] = myinf;
-    }
-    if (c.lane < L * D)
-        c.slot_all()[c.lane] = c.lane % L;
-    wave_sync();
+    // the candidate's metric (Eq. (10)) and its index and sign
+    const uint64_t kb = (uint64_t)__double_as_longlong(mykey);
+    const float mypm = pm + 0.5f * (sabs - __uint_as_float((uint32_t)(kb >> 32)));
+    const uint32_t myinf = (uint32_t)kb & 0xFFFu;
+
+    // stable merge of the L*K candidates by metric, keep L (Alg. 3).  Each
+    // path's K candidates are already in metric order (the metric does not
+    // decrease as |F| decreases), so the lists are merged by a bitonic
+    // network over lanes.  Merge key: the metric's bits (metrics are
+    // non-negative, since |F| <= sum |alpha| holds in floating point: both
+    // sums follow the same pairing tree) over (e = g*K + t, index, sign),
+    // so ties go to the lower enumeration position e.
     static_assert(K == L, "list merge assumes min(L, 2^s) = L");
-    select_smallest<L * K, L, D, L * L>(c.cpm_all(), c.slot_all(), c.lane);
-    wave_sync();
-    const int e = slot[c.g];
-    const float opm = cpm[e];
-    const uint32_t inf = cinf[e];
-    wave_sync();
+    int e;
+    float opm;
+    uint32_t inf;
+    if constexpr (L == 1) {
+        e = 0;
+        opm = mypm;
+        inf = myinf;
+    } else {
+        const uint32_t mlo = ((uint32_t)(c.g * K + lg) << 12) | myinf;
+        double mk = __longlong_as_double((long long)(((uint64_t)__float_as_uint(mypm) << 32) | mlo));
+        mk = merge_lists<0, L, K, G>(mk, lg);
+        // survivor l sits in lane l of the decoder's first group
+        const uint64_t sk = (uint64_t)__double_as_longlong(from_lane(mk, c.lead_of(0) + c.g));
+        e = (int)((uint32_t)sk >> 12);
+        opm = __uint_as_float((uint32_t)(sk >> 32));
+        inf = (uint32_t)sk & 0xFFFu;
+    }
 
     // codeword of transform index idx: x(z) = [F<0] ^ parity(cw) ^ parity(cw & z), cw = n-1-idx
     const uint32_t idx = 1024u - (inf >> 1);
