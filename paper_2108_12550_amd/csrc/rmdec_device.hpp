@@ -398,6 +398,34 @@ __device__ __forceinline__ double merge_lists(double key, int lg)
     }
 }
 
+// Bitonic sort, ascending, of 2^NB keys held one per lane: key k sits in
+// lane (k >> 1) * G + (k & 1) relative to the decoder's first lane, so bit 0
+// of k is a lane bit and bit d >= 1 is lane bit log2(G) + d - 1.
+template <int NB, int G, int SZ, int ST>
+__device__ __forceinline__ double bitonic_sort_step(double key, int k)
+{
+    constexpr int X = ST == 0 ? 1 : (G << (ST - 1));
+    const double o = xor64<X>(key);
+    const bool asc = SZ == NB || ((k >> SZ) & 1) == 0;
+    const bool lower = ((k >> ST) & 1) == 0;
+    const double mn = dmin(key, o), mx = dmax(key, o);
+    const double r = (lower == asc) ? mn : mx;
+    if constexpr (ST > 0)
+        return bitonic_sort_step<NB, G, SZ, ST - 1>(r, k);
+    else if constexpr (SZ < NB)
+        return bitonic_sort_step<NB, G, SZ + 1, SZ>(r, k);
+    else
+        return r;
+}
+template <int NB, int G>
+__device__ __forceinline__ double bitonic_sort(double key, int k)
+{
+    if constexpr (NB == 0)
+        return key;
+    else
+        return bitonic_sort_step<NB, G, 1, 0>(key, k);
+}
+
 // Byte addresses of elements p(i), i = lg + G j (j < RR), of a vector at
 // byte address `base` (aligned to the vector's size, so XOR acts as
 // addition), under an affine map on F2^MD stored in LDS as byte-scaled
@@ -531,11 +559,11 @@ __device__ __forceinline__ NodeRes<(1 << S), kWave / (L * D)> fhtl(const Ctx<M, 
         if (K == 1 || lg == t) // one round: every lane of the group holds the winner
             mykey = w;
         if (t + 1 < K) {
+            // (b3 need not be cleared: once `left` reaches 0 the lane rescans)
             const bool own = valid && (b1 == w);
             if (own) {
                 b1 = b2;
                 b2 = b3;
-                b3 = 0.0;
                 left--;
             }
             const bool need = own && left == 0;
@@ -694,34 +722,28 @@ __device__ __forceinline__ NodeRes<(1 << S), kWave / (L * D)> spcl(const Ctx<M, 
     int src = g;
     uint32_t flips = 0;
     uint32_t p = par;
-    float *cpm = c.cpm();
-    uint32_t *cinf = c.cinf();
-    uint32_t *caux = c.caux();
-    int *slot = c.slot();
     wave_sync();
 #pragma unroll
     for (int t = 1; t <= tau; t++) {
-        // (keep, flip o_t) for every path in list order; Eqs. (4) and (5)
+        // (keep, flip o_t) for every path in list order, Eqs. (4) and (5):
+        // candidate e = 2g + lg (lg < 2).  Stable selection of the L
+        // smallest: bitonic sort of the 2L keys (metric bits over e, then
+        // the candidate's state as payload; metrics are non-negative).
         const float at = spca[src * TS + t];
         const float as0 = spca[src * TS];
         const float fpm = (cur + at) + (p ? -as0 : as0);
-        if (lg < 2) {
-            const int e = 2 * g + lg;
-            cpm[e] = lg ? fpm : cur;
-            cinf[e] = (uint32_t)src | ((lg ? (p ^ 1u) : p) << 8);
-            caux[e] = lg ? (flips | (1u << t)) : flips;
-        }
-        if (c.lane < L * D)
-            c.slot_all()[c.lane] = c.lane % L;
-        wave_sync();
-        select_smallest<2 * L, L, D, L * L>(c.cpm_all(), c.slot_all(), c.lane);
-        wave_sync();
-        const int e = slot[g];
-        cur = cpm[e];
-        src = (int)(cinf[e] & 0xFFu);
-        p = (cinf[e] >> 8) & 1u;
-        flips = caux[e];
-        wave_sync();
+        const int e = 2 * g + (lg & 1);
+        const uint32_t st = (lg & 1) ? ((flips | (1u << t)) << 8) | ((uint32_t)src << 1) | (p ^ 1u)
+                                     : (flips << 8) | ((uint32_t)src << 1) | p;
+        double key = __longlong_as_double(
+            (long long)(((uint64_t)__float_as_uint((lg & 1) ? fpm : cur) << 32) | ((uint32_t)e << 24) | st));
+        key = bitonic_sort<ilog2(2 * L), G>(key, e);
+        // this group's path takes rank g
+        const uint64_t sk = (uint64_t)__double_as_longlong(from_lane(key, c.lead_of(g >> 1) + (g & 1)));
+        cur = __uint_as_float((uint32_t)(sk >> 32));
+        p = (uint32_t)sk & 1u;
+        src = (int)(((uint32_t)sk >> 1) & 0x7Fu);
+        flips = ((uint32_t)sk >> 8) & 0xFFFFu;
     }
 
     // codeword: hard decisions of the source path, the taken flips, then the
