@@ -179,6 +179,15 @@ __device__ __forceinline__ double from_lane(double v, int src)
     return __longlong_as_double((long long)from_lane((uint64_t)__double_as_longlong(v), src));
 }
 
+// forward permute: this lane's value goes to lane `dst` (destinations distinct)
+__device__ __forceinline__ double to_lane(double v, int dst)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_permute(dst << 2, (int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_permute(dst << 2, (int)(uint32_t)(u >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 // butterflies over aligned blocks of 2W lanes (W = 2^k or 0); every lane of
 // a block ends with the same value
 template <int W>
@@ -499,16 +508,53 @@ __device__ __forceinline__ MaskT walsh_mask(uint32_t c)
     return w;
 }
 
-// FHT key: a 64-bit pattern with the bits of |F| as its high word and
-// ((1024 - i) << 1 | sign of F) as its low word.  Read as a double it is
-// positive and finite, and doubles of one sign order like their bit
-// patterns, so one v_max_f64 orders keys by |F| (larger first), then by the
-// index (lower first).  The low word is one funnel shift of (1024 - i, F).
-__device__ __forceinline__ double fht_key(float f, uint32_t i)
+// FHT keys.  A key is a 64-bit pattern read as a double: the bits of F as
+// its high word and, as its low word, an index code and the sign of F:
+//   lo = ((KB - j) << (LG + 1)) | ((G - 1 - lg) << 1) | [F < 0]
+// for element i = lg + G*j (KB = 1024/G), so that lo >> 1 = KI - i with
+// KI = 1024 + G - 1.  Doubles of one sign order like their bit patterns, and
+// the selection takes |key| (an abs modifier: sign of the high word cleared),
+// so max(|key|) orders by |F| (larger first), then by the index (lower
+// first).  A lane builds the part without its lane bits with one funnel
+// shift; the lane bits are added once to its few retained keys.
+__device__ __forceinline__ double fht_key_part(float f, uint32_t jcode)
 {
     const uint32_t fb = __float_as_uint(f);
-    const uint32_t lo = __builtin_amdgcn_alignbit(1024u - i, fb, 31u);
-    return __longlong_as_double((long long)(((uint64_t)(fb & 0x7FFFFFFFu) << 32) | lo));
+    const uint32_t lo = __builtin_amdgcn_alignbit(jcode, fb, 31u);
+    return __longlong_as_double((long long)(((uint64_t)fb << 32) | lo));
+}
+template <int G>
+__device__ __forceinline__ uint32_t fht_jcode(int j)
+{
+    return (uint32_t)((1024 / G - j) << ilog2(G));
+}
+__device__ __forceinline__ double key_or_lo(double k, uint32_t bits)
+{
+    return __longlong_as_double((long long)((uint64_t)__double_as_longlong(k) | bits));
+}
+// max/min of |a| and b (b non-negative)
+__device__ __forceinline__ double dmax_abs(double b, double a)
+{
+    double r;
+    asm("v_max_f64 %0, %1, |%2|" : "=v"(r) : "v"(b), "v"(a));
+    return r;
+}
+__device__ __forceinline__ double dmin_abs(double b, double a)
+{
+    double r;
+    asm("v_min_f64 %0, %1, |%2|" : "=v"(r) : "v"(b), "v"(a));
+    return r;
+}
+
+// rank of key k among the n keys of lanes lg ^ W, W < n (larger first; keys
+// are distinct)
+template <int W, int n>
+__device__ __forceinline__ void fht_rank(double k, int &rank)
+{
+    if constexpr (W < n) {
+        rank += xor64<W>(k) > k;
+        fht_rank<W + 1, n>(k, rank);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -537,63 +583,86 @@ __device__ __forceinline__ NodeRes<(1 << S), kWave / (L * D)> fhtl(const Ctx<M, 
 
     fht_stages<n / 2, G, RR>(A, lg);
 
-    // lane-local three largest keys
-    double b1 = 0.0, b2 = 0.0, b3 = 0.0;
+    const uint32_t lanebits = (uint32_t)(G - 1 - lg) << 1;
+    float mypm;       // metric of this lane's candidate (Eq. (10))
+    uint32_t myinf;   // its index code and sign
+    int cand;         // its position t in the path's candidate order
+    if constexpr (n <= G && K > 1) {
+        // one element per lane: its rank among the node's n keys (larger
+        // first) is its position; ranks below K are the candidates
+        const double k = valid ? key_or_lo(fht_key_part(A[0], fht_jcode<G>(0)), lanebits) : 0.0;
+        const double ka = fabs(k);
+        int rank = 0;
+        fht_rank<1, n>(ka, rank);
+        cand = valid ? rank : lg;
+        const uint64_t kb = (uint64_t)__double_as_longlong(k);
+        mypm = pm + 0.5f * (sabs - fabsf(__uint_as_float((uint32_t)(kb >> 32))));
+        myinf = (uint32_t)kb & 0xFFFu;
+    } else {
+        // lane-local three largest keys (without lane bits: one lane, one lg)
+        double b1 = 0.0, b2 = 0.0, b3 = 0.0;
 #pragma unroll
-    for (int j = 0; j < RR; j++) {
-        const double k = valid ? fht_key(A[j], (uint32_t)(lg + G * j)) : 0.0;
-        const double x1 = dmin(b1, k);
-        b1 = dmax(b1, k);
-        const double x2 = dmin(b2, x1);
-        b2 = dmax(b2, x1);
-        b3 = dmax(b3, x2);
-    }
-    int left = 3; // keys of this lane known to be its largest below the last pop
+        for (int j = 0; j < RR; j++) {
+            const double k = valid ? fht_key_part(A[j], fht_jcode<G>(j)) : 0.0;
+            const double x1 = dmin_abs(b1, k);
+            b1 = dmax_abs(b1, k);
+            const double x2 = dmin(b2, x1);
+            b2 = dmax(b2, x1);
+            b3 = dmax(b3, x2);
+        }
+        if (valid) {
+            b1 = key_or_lo(b1, lanebits);
+            b2 = key_or_lo(b2, lanebits);
+            b3 = key_or_lo(b3, lanebits);
+        }
+        int left = 3; // keys of this lane known to be its largest below the last pop
 
-    // K rounds: the group's largest remaining key is the next candidate;
-    // lane t of the group keeps the key of round t
-    double mykey = 0.0;
+        // K rounds: the group's largest remaining key is the next candidate;
+        // lane t of the group keeps the key of round t
+        double mykey = 0.0;
 #pragma unroll
-    for (int t = 0; t < K; t++) {
-        const double w = bfly_max<ACT / 2>(b1);
-        if (K == 1 || lg == t) // one round: every lane of the group holds the winner
-            mykey = w;
-        if (t + 1 < K) {
-            // (b3 need not be cleared: once `left` reaches 0 the lane rescans)
-            const bool own = valid && (b1 == w);
-            if (own) {
-                b1 = b2;
-                b2 = b3;
-                left--;
-            }
-            const bool need = own && left == 0;
-            if (__any(need)) {
-                // the owner used up its known keys: rescan below w
-                double n1 = 0.0, n2 = 0.0, n3 = 0.0;
-#pragma unroll
-                for (int j = 0; j < RR; j++) {
-                    double k = valid ? fht_key(A[j], (uint32_t)(lg + G * j)) : 0.0;
-                    k = k < w ? k : 0.0;
-                    const double x1 = dmin(n1, k);
-                    n1 = dmax(n1, k);
-                    const double x2 = dmin(n2, x1);
-                    n2 = dmax(n2, x1);
-                    n3 = dmax(n3, x2);
+        for (int t = 0; t < K; t++) {
+            const double w = bfly_max<ACT / 2>(b1);
+            if (K == 1 || lg == t) // one round: every lane of the group holds the winner
+                mykey = w;
+            if (t + 1 < K) {
+                // (b3 need not be cleared: once `left` reaches 0 the lane rescans)
+                const bool own = valid && (b1 == w);
+                if (own) {
+                    b1 = b2;
+                    b2 = b3;
+                    left--;
                 }
-                if (need) {
-                    b1 = n1;
-                    b2 = n2;
-                    b3 = n3;
-                    left = 3;
+                const bool need = own && left == 0;
+                if (__any(need)) {
+                    // the owner used up its known keys: rescan below w
+                    double n1 = 0.0, n2 = 0.0, n3 = 0.0;
+#pragma unroll
+                    for (int j = 0; j < RR; j++) {
+                        double k = valid ? key_or_lo(fht_key_part(A[j], fht_jcode<G>(j)), lanebits) : 0.0;
+                        k = fabs(k) < w ? k : 0.0;
+                        const double x1 = dmin_abs(n1, k);
+                        n1 = dmax_abs(n1, k);
+                        const double x2 = dmin(n2, x1);
+                        n2 = dmax(n2, x1);
+                        n3 = dmax(n3, x2);
+                    }
+                    if (need) {
+                        b1 = n1;
+                        b2 = n2;
+                        b3 = n3;
+                        left = 3;
+                    }
                 }
             }
         }
-    }
 
-    // the candidate's metric (Eq. (10)) and its index and sign
-    const uint64_t kb = (uint64_t)__double_as_longlong(mykey);
-    const float mypm = pm + 0.5f * (sabs - __uint_as_float((uint32_t)(kb >> 32)));
-    const uint32_t myinf = (uint32_t)kb & 0xFFFu;
+        // the candidate's metric (Eq. (10)) and its index and sign
+        const uint64_t kb = (uint64_t)__double_as_longlong(mykey);
+        mypm = pm + 0.5f * (sabs - __uint_as_float((uint32_t)(kb >> 32)));
+        myinf = (uint32_t)kb & 0xFFFu;
+        cand = lg;
+    }
 
     // stable merge of the L*K candidates by metric, keep L (Alg. 3).  Each
     // path's K candidates are already in metric order (the metric does not
@@ -611,8 +680,10 @@ __device__ __forceinline__ NodeRes<(1 << S), kWave / (L * D)> fhtl(const Ctx<M, 
         opm = mypm;
         inf = myinf;
     } else {
-        const uint32_t mlo = ((uint32_t)(c.g * K + lg) << 12) | myinf;
+        const uint32_t mlo = ((uint32_t)(c.g * K + cand) << 12) | myinf;
         double mk = __longlong_as_double((long long)(((uint64_t)__float_as_uint(mypm) << 32) | mlo));
+        if constexpr (n <= G) // to lane t of the group for candidate t
+            mk = to_lane(mk, c.lead_of(c.g) + cand);
         mk = merge_lists<0, L, K, G>(mk, lg);
         // survivor l sits in lane l of the decoder's first group
         const uint64_t sk = (uint64_t)__double_as_longlong(from_lane(mk, c.lead_of(0) + c.g));
@@ -622,7 +693,7 @@ __device__ __forceinline__ NodeRes<(1 << S), kWave / (L * D)> fhtl(const Ctx<M, 
     }
 
     // codeword of transform index idx: x(z) = [F<0] ^ parity(cw) ^ parity(cw & z), cw = n-1-idx
-    const uint32_t idx = 1024u - (inf >> 1);
+    const uint32_t idx = (uint32_t)(1024 + G - 1) - (inf >> 1);
     const uint32_t cw = (uint32_t)(n - 1) - idx;
     const uint32_t b0 = (inf & 1u) ^ (__popc(cw) & 1u);
     const uint32_t lbit = b0 ^ (__popc(cw & (uint32_t)lg) & 1u);
