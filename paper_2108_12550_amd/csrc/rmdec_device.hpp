@@ -281,6 +281,8 @@ template <int M, int R, int L, int D>
 struct Shape {
     static constexpr int N = 1 << M;
     static constexpr int G = kWave / (L * D); // lanes per path; D decoders of L paths per wave
+    // the candidate merges hold one candidate per lane of a path's group
+    static_assert(L <= G && 2 <= G, "at least max(L, 2) lanes per path");
     static constexpr int LG = ilog2(G);
     static constexpr int NPERM = perm_spine(M, R);
     static constexpr bool ROOT_LEAF = !(1 < R && R < M - 1);

@@ -27,11 +27,16 @@ hipError_t launch_decode(const KernelArgs &args, int blocks, hipStream_t stream)
 }
 
 // Decoders per wavefront: D*L = 8 paths share the 64 lanes (8 lanes per
-// path); for N = 1024 only 4 paths (16 lanes per path), which keeps a
-// half-length node vector at 32 registers.  WPE: wavefronts per SIMD the
-// register allocation must allow (3: at most 168 VGPRs; 2: 256).  These
-// choices keep every kernel free of (or nearly free of) register spills.
-constexpr int decoders_per_wave(int M, int L) { return L >= 8 ? 1 : (M >= 10 ? 4 : 8) / L; }
+// path); for N <= 256 at L = 4, 16 paths (4 lanes per path: per-node fixed
+// costs are shared by twice the decoders); for N = 1024 only 4 paths (16
+// lanes per path), which keeps a half-length node vector at 32 registers.
+// WPE: wavefronts per SIMD the register allocation must allow (3: at most
+// 168 VGPRs; 2: 256).  These choices keep every kernel free of (or nearly
+// free of) register spills.
+constexpr int decoders_per_wave(int M, int L)
+{
+    return L >= 8 ? 1 : (M >= 10 ? 4 : (M <= 8 && L == 4) ? 16 : 8) / L;
+}
 constexpr int waves_per_eu(int M, int L) { return M >= 10 && L >= 8 ? 2 : 3; }
 
 template <int M, int R, int L, int D = decoders_per_wave(M, L), int WPE = waves_per_eu(M, L)>

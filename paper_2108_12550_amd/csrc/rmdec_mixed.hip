@@ -16,22 +16,23 @@ using namespace rmdec;
 namespace {
 
 // The codes compiled into the fused kernel: RM(2,7), RM(2,8), RM(2,9) and
-// RM(2,10), list size 4; two decoders per wavefront, one for RM(2,10)
-// (the per-code kernels make the same choices).
+// RM(2,10), list size 4; four decoders per wavefront for RM(2,7) and
+// RM(2,8), two for RM(2,9), one for RM(2,10) (the per-code kernels make the
+// same choices).
 constexpr int kWPE = 3;
 
 constexpr int kFused[][3] = {{7, 2, 4}, {8, 2, 4}, {9, 2, 4}, {10, 2, 4}};
 constexpr int kNumFused = 4;
-constexpr int kFusedBytes = MaxBytes<Code<7, 2, 4, 2>, Code<8, 2, 4, 2>, Code<9, 2, 4, 2>, Code<10, 2, 4, 1>>::value;
+constexpr int kFusedBytes = MaxBytes<Code<7, 2, 4, 4>, Code<8, 2, 4, 4>, Code<9, 2, 4, 2>, Code<10, 2, 4, 1>>::value;
 
 const void *fused_kernel()
 {
-    return (const void *)&rm_mixed_kernel<kWPE, Code<7, 2, 4, 2>, Code<8, 2, 4, 2>, Code<9, 2, 4, 2>, Code<10, 2, 4, 1>>;
+    return (const void *)&rm_mixed_kernel<kWPE, Code<7, 2, 4, 4>, Code<8, 2, 4, 4>, Code<9, 2, 4, 2>, Code<10, 2, 4, 1>>;
 }
 
 hipError_t launch_fused(const MixedArgs &a, int blocks, hipStream_t s)
 {
-    hipLaunchKernelGGL((rm_mixed_kernel<kWPE, Code<7, 2, 4, 2>, Code<8, 2, 4, 2>, Code<9, 2, 4, 2>, Code<10, 2, 4, 1>>),
+    hipLaunchKernelGGL((rm_mixed_kernel<kWPE, Code<7, 2, 4, 4>, Code<8, 2, 4, 4>, Code<9, 2, 4, 2>, Code<10, 2, 4, 1>>),
                        dim3(blocks), dim3(kWave * a.waves), (size_t)a.waves * kFusedBytes, s, a);
     return hipGetLastError();
 }

@@ -91,7 +91,7 @@ def test_mixed_codes_l4(m, P):
 
 # --- the tree shapes and list sizes ---
 
-@pytest.mark.parametrize("m,r", [(4, 2), (5, 2), (6, 2), (5, 3), (6, 3), (7, 3), (8, 2), (9, 2)])
+@pytest.mark.parametrize("m,r", [(4, 2), (5, 2), (6, 2), (5, 3), (6, 3), (7, 3), (8, 2), (9, 2), (8, 3), (7, 2)])
 @pytest.mark.parametrize("L", [1, 2, 4, 8])
 def test_codes_and_lists(m, r, L):
     _, llr = synth.frames(m, r, 70, 1.0, seed=100 + m * 10 + r)
