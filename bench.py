@@ -39,7 +39,7 @@ SEED = 0
 OPS_PER_FRAME = 4.2e5
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
-KERNEL_NAME = "rm_decode_kernel<9, 2, 4, 2, 3>"  # (m, r, L, decoders per wave, waves per SIMD)
+KERNEL_NAME = "rm_decode_kernel<9, 2, 4, 2, 4>"  # (m, r, L, decoders per wave, waves per SIMD)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rm_decode_rm29_p20_l4_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2108_12550_amd", "csrc", f)
                   for f in ("rmdec_device.hpp", "rmdec_kernels.hpp", "rmdec_inst_a.hip")]

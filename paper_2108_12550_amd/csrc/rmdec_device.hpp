@@ -30,7 +30,8 @@ namespace rmdec {
 
 constexpr int kWave = 64;
 
-// Words per stored affine map: col[0..11], b at [12], m at [13].
+// Words per stored affine map: col[0..11], b at [12] (both times 4: byte
+// offsets of float elements), m at [13].
 constexpr int kMapWords = 16;
 constexpr int kMapB = 12;
 
@@ -387,9 +388,11 @@ __device__ __forceinline__ double bitonic_clean(double key, int lg)
     if constexpr (S == 0) {
         return key;
     } else {
+        // keys are distinct: keep this lane's key if it is on the side the
+        // lane wants (the smaller in the lower lane of the pair)
         const double o = xor64<S>(key);
-        const double lo = dmin(key, o), hi = dmax(key, o);
-        return bitonic_clean<S / 2>((lg & S) ? hi : lo, lg);
+        const bool keep = (key < o) != ((lg & S) != 0);
+        return bitonic_clean<S / 2>(keep ? key : o, lg);
     }
 }
 
@@ -419,8 +422,9 @@ __device__ __forceinline__ double bitonic_sort_step(double key, int k)
     const double o = xor64<X>(key);
     const bool asc = SZ == NB || ((k >> SZ) & 1) == 0;
     const bool lower = ((k >> ST) & 1) == 0;
-    const double mn = dmin(key, o), mx = dmax(key, o);
-    const double r = (lower == asc) ? mn : mx;
+    // keys are distinct: keep this lane's key if it is on the side the lane wants
+    const bool keep = (key < o) == (lower == asc);
+    const double r = keep ? key : o;
     if constexpr (ST > 0)
         return bitonic_sort_step<NB, G, SZ, ST - 1>(r, k);
     else if constexpr (SZ < NB)
@@ -1135,11 +1139,11 @@ __device__ __forceinline__ void decode_frame(const KernelArgs &args, const float
 #pragma unroll
         for (int t = 0; t < D; t++) {
             const int dd = d0 + t < args.P ? d0 + t : args.P - 1;
-            const uint32_t *mg = args.maps + (size_t)dd * args.maps_per_dec * kMapWords;
-            uint32_t *ml = c.maps_all() + t * Sh::MAPS_PER_DEC * kMapWords;
-            // columns and offset as byte offsets of float elements
-            for (int i = c.lane; i < args.maps_per_dec * kMapWords; i += kWave)
-                ml[i] = (i % kMapWords) <= kMapB ? mg[i] << 2 : mg[i];
+            // stored with columns and offset as byte offsets of float elements
+            const uint4 *mg = (const uint4 *)(args.maps + (size_t)dd * args.maps_per_dec * kMapWords);
+            uint4 *ml = (uint4 *)(c.maps_all() + t * Sh::MAPS_PER_DEC * kMapWords);
+            for (int i = c.lane; i < args.maps_per_dec * (kMapWords / 4); i += kWave)
+                ml[i] = mg[i];
         }
         wave_sync();
         const RootRes<M, R, L, D> r = decode_root<M, R, L, D>(c);
@@ -1174,8 +1178,8 @@ __device__ __forceinline__ void decode_frame(const KernelArgs &args, const float
     uint32_t col[M + 1];
 #pragma unroll
     for (int k = 0; k < M; k++)
-        col[k] = mi[k];
-    col[M] = mi[kMapB];
+        col[k] = mi[k] >> 2;
+    col[M] = mi[kMapB] >> 2;
 #pragma unroll
     for (int j0 = 0; j0 < N; j0 += kWave) {
         const uint32_t j = (uint32_t)(j0 + c.lane);

@@ -159,13 +159,16 @@ Draw draw_all(int m, int r, int P, int L, uint64_t seed, int pfht)
 
 // A map as the kernel stores it: images of the unit vectors (columns) and b,
 // obtained from the full permutation table q[i].
+// One stored map: the images of the unit vectors (columns) and the offset,
+// each times 4 (byte offsets of float elements, the form the kernels XOR into
+// LDS addresses), then the dimension.
 void store_table(const std::vector<uint32_t> &q, int m, uint32_t *out)
 {
     for (int k = 0; k < kMapWords; k++)
         out[k] = 0;
     for (int k = 0; k < m; k++)
-        out[k] = q[1u << k] ^ q[0];
-    out[kMapB] = q[0];
+        out[k] = (q[1u << k] ^ q[0]) << 2;
+    out[kMapB] = q[0] << 2;
     out[13] = (uint32_t)m;
 }
 
