@@ -41,7 +41,8 @@ extern "C" {
 /* RM_E_AGAIN (-6) is defined with the request server below */
 
 /* Permutation mode. */
-#define RM_PERM_NONE 0 /* FHT-FSCL: identity, no permutation domain (needs L = 1) */
+#define RM_PERM_NONE 0 /* FHT-FSCL: identity, no permutation domain; the list starts
+                          from one path, the other L-1 entries inactive            */
 #define RM_PERM_PFHT 1 /* p-FHT-FSCL: random affine permutations (Alg. 2)         */
 
 typedef struct rm_decoder rm_decoder;

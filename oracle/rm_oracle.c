@@ -505,10 +505,6 @@ rmo_decoder *rmo_create(int m, int r, int P, int L, int perm_mode, uint64_t seed
         return NULL;
     if (perm_mode != RMO_PERM_NONE && perm_mode != RMO_PERM_PFHT)
         return NULL;
-    /* Without permutations the L paths would start as L copies of one path;
-     * the single-active-path start of plain FHT-FSCL is not modelled here. */
-    if (perm_mode == RMO_PERM_NONE && L != 1)
-        return NULL;
     rmo_decoder *d = calloc(1, sizeof *d);
     d->m = m;
     d->r = r;
@@ -782,7 +778,12 @@ int rmo_decode(const rmo_decoder *d, const float *y, uint8_t *xhat, float *pm)
             const amap *ai = &d->init[(size_t)p * L + l];
             for (int i = 0; i < n; i++)
                 a[l][i] = y[amap_apply(ai, (uint32_t)i)];
-            pm0[l] = 0.0f;
+            /* Alg. 2 starts its L paths from L different permutations.
+             * Plain FHT-FSCL (no permutations) starts from one path: list
+             * entries 1..L-1 begin inactive, with an infinite metric, so
+             * they never displace a finite candidate and the list fills
+             * through the path splits alone. */
+            pm0[l] = (d->mode == RMO_PERM_PFHT || l == 0) ? 0.0f : INFINITY;
         }
         ctx_t c = {d, p, d->mode == RMO_PERM_PFHT, 0};
         node_decode(&c, d->r, m, a, pm0, x, pmo, anc);

@@ -15,7 +15,8 @@
 #define RM_ORACLE_H
 #include <stdint.h>
 
-#define RMO_PERM_NONE 0   /* FHT-FSCL: identity, no permutation domain */
+#define RMO_PERM_NONE 0   /* FHT-FSCL: identity, no permutation domain; the
+                             list starts from one path (others inactive)   */
 #define RMO_PERM_PFHT 1   /* p-FHT-FSCL: Alg. 2 permutation domain      */
 
 typedef struct rmo_decoder rmo_decoder;

@@ -1048,6 +1048,9 @@ __device__ __forceinline__ RootRes<M, R, L, D> decode_root(const Ctx<M, R, L, D>
     constexpr int N = Sh::N;
     constexpr int G = Sh::G;
     const uint32_t *maps = c.maps();
+    // Alg. 2 starts its L paths from L permutations; without permutations the
+    // list starts from one path, the other entries inactive (infinite metric)
+    const float pm0 = (c.pfht || c.g == 0) ? 0.0f : __builtin_inff();
     if constexpr (!Sh::ROOT_LEAF) {
         constexpr int h = N / 2;
         using Lc = Lay<h, G>;
@@ -1065,7 +1068,7 @@ __device__ __forceinline__ RootRes<M, R, L, D> decode_root(const Ctx<M, R, L, D>
             for (int j = 0; j < RC; j++)
                 C[j] = f_minsum(lds_f32(pos[j]), lds_f32(pos[j] ^ colh));
         }
-        const auto rl = node<M, R, L, D, M - 1, R - 1, true>(c, C, 0.0f);
+        const auto rl = node<M, R, L, D, M - 1, R - 1, true>(c, C, pm0);
         {
             const uint32_t *mp = maps + from_lane(rmap, c.lead_of(rl.anc)) * kMapWords;
             uint32_t pos[RC];
@@ -1093,9 +1096,9 @@ __device__ __forceinline__ RootRes<M, R, L, D> decode_root(const Ctx<M, R, L, D>
         }
         NodeRes<N, G> res;
         if constexpr (R == 1)
-            res = fhtl<M, R, L, D, M>(c, A, 0.0f);
+            res = fhtl<M, R, L, D, M>(c, A, pm0);
         else
-            res = spcl<M, R, L, D, M>(c, A, 0.0f);
+            res = spcl<M, R, L, D, M>(c, A, pm0);
         return {(uint64_t)res.x, 0ull, res.pm, L + res.anc};
     }
 }

@@ -210,8 +210,6 @@ int check_params(int m, int r, int P, int L, int perm_mode)
         return fail(RM_E_INVAL, "L must be 1, 2, 4 or 8");
     if (perm_mode != RM_PERM_NONE && perm_mode != RM_PERM_PFHT)
         return fail(RM_E_INVAL, "unknown perm_mode");
-    if (perm_mode == RM_PERM_NONE && L != 1)
-        return fail(RM_E_UNSUPPORTED, "perm_mode NONE needs L = 1");
     return RM_OK;
 }
 

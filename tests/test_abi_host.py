@@ -58,9 +58,9 @@ def test_invalid_parameters_rejected(args):
     assert rmd.rm_last_error()
 
 
-def test_none_mode_needs_single_path():
-    n, *_ = _lib.rm_perm_tables(7, 2, 1, 4, 0, rmd.RM_PERM_NONE, 64)
-    assert n == _lib.RM_E_UNSUPPORTED
+def test_none_mode_with_list_draws_identities():
+    maps = rmd.perm_tables(7, 2, 1, 4, 0, rmd.RM_PERM_NONE)
+    assert maps == [([1 << k for k in range(7)], 0)] * 4
 
 
 def test_small_cap_rejected():

@@ -319,9 +319,30 @@ def test_exhaustive_ml_rm25():
     assert agree / llr.shape[0] >= 0.99
 
 
-def test_none_mode_requires_single_path():
-    with pytest.raises(ValueError):
-        oracle.OracleDecoder(7, 2, 1, 4, perm_mode=oracle.PERM_NONE)
+@pytest.mark.parametrize("m,r,L", [(5, 2, 2), (6, 3, 4), (7, 2, 8), (5, 3, 4)])
+def test_plain_list_decoder_outputs_codewords_and_metric_identity(m, r, L):
+    """FHT-FSCL-L without permutations (one active path at the start): every
+    output is a codeword and the metric is the correlation metric."""
+    dec = oracle.OracleDecoder(m, r, 1, L, perm_mode=oracle.PERM_NONE)
+    _, llr = synth.frames(m, r, 60, 1.5, seed=3 * L + m)
+    for f in range(llr.shape[0]):
+        x, pm = dec.decode(llr[f])
+        assert np.isfinite(pm)
+        assert is_codeword(x, m, r), f
+        y = llr[f].astype(np.float64)
+        corr = np.abs(y[(x.astype(bool)) != (y < 0)]).sum()
+        assert abs(pm - corr) <= 1e-4 * max(1.0, corr)
+
+
+def test_plain_list_of_one_equals_l1_and_noiseless():
+    """L = 1 in the plain mode is FHT-FSC; noiseless frames come back exact
+    at any L (the inactive entries never win)."""
+    x, llr = synth.frames(7, 2, 50, 40.0, seed=8)
+    for L in (1, 2, 4, 8):
+        dec = oracle.OracleDecoder(7, 2, 1, L, perm_mode=oracle.PERM_NONE)
+        bits, pm = dec.decode_batch(llr, n_threads=2)
+        assert np.array_equal(synth.unpack_bits(bits, 128), x)
+        assert np.all(pm == 0.0)
 
 
 # --------------------------------------------------------------------------
@@ -335,6 +356,20 @@ def _fer(m, r, P, L, mode, ebn0, n, seed):
     bits, _ = dec.decode_batch(llr, n_threads=os.cpu_count() or 1)
     xh = synth.unpack_bits(bits, 1 << m)
     return int(np.any(xh != x, axis=1).sum())
+
+
+@pytest.mark.parametrize("name,L,ebn0,n", [
+    ("FHT-FSCL-2", 2, "3.0", 6000),
+    ("FHT-FSCL-4", 4, "3.0", 8000),
+    ("FHT-FSCL-8", 8, "2.5", 6000),
+])
+def test_plain_list_fer_matches_fig5(name, L, ebn0, n):
+    """FHT-FSCL-L without permutations against its deterministic curves in
+    Fig. 5(a): pins the single-active-path start of the plain list decoder."""
+    pub = GOLDEN["fer_rm29_plain"][name][ebn0]
+    k = _fer(9, 2, 1, L, oracle.PERM_NONE, float(ebn0), n, seed=41)
+    lo, hi = wilson(k, n, 3.29)  # 99.9% interval
+    assert lo <= pub <= hi, (name, ebn0, k / n, pub)
 
 
 @pytest.mark.parametrize("name,mode,L,ebn0,n", [
