@@ -106,7 +106,7 @@ def test_leaf_roots(m, r, L):
 
 
 @pytest.mark.parametrize("m,r,L", [(7, 2, 2), (7, 2, 4), (9, 2, 4), (9, 2, 8), (8, 3, 4), (8, 3, 8), (10, 2, 4),
-                                   (5, 2, 8), (6, 1, 4), (4, 3, 2)])
+                                   (5, 2, 8), (6, 1, 4), (4, 3, 4)])
 def test_plain_list_mode(m, r, L):
     """FHT-FSCL-L without permutations: one active path at the start."""
     _, llr = synth.frames(m, r, 150, 2.0, seed=300 + m * 10 + L)
