@@ -130,6 +130,15 @@ __device__ __forceinline__ uint32_t xor_any(uint32_t v)
         return xor_quad<W>(v);
 }
 
+// 64-bit value held by lane (lane ^ W)
+template <int W>
+__device__ __forceinline__ double xor64(double v)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint64_t r = ((uint64_t)xor_any<W>((uint32_t)(u >> 32)) << 32) | xor_any<W>((uint32_t)u);
+    return __longlong_as_double((long long)r);
+}
+
 template <int W>
 __device__ __forceinline__ float xor_lanes(float v)
 {
@@ -189,6 +198,13 @@ __device__ __forceinline__ double to_lane(double v, int dst)
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
+// Partner distance for the level of an order-free butterfly (max, xor) that
+// stands for distance W: within 8 lanes, XOR 7 is one DPP move (row half
+// mirror) where XOR 4 takes two, and {7, 2, 1} spans the block like
+// {4, 2, 1}.  Sums keep the distances of the canonical halving tree.
+template <int W>
+constexpr int span_xor() { return W == 4 ? 7 : W; }
+
 // butterflies over aligned blocks of 2W lanes (W = 2^k or 0); every lane of
 // a block ends with the same value
 template <int W>
@@ -203,7 +219,7 @@ template <int W>
 __device__ __forceinline__ double bfly_max(double v)
 {
     if constexpr (W >= 1)
-        return bfly_max<W / 2>(dmax(v, xor_lanes<W>(v)));
+        return bfly_max<W / 2>(dmax(v, xor64<span_xor<W>()>(v)));
     else
         return v;
 }
@@ -211,7 +227,7 @@ template <int W>
 __device__ __forceinline__ uint64_t bfly_umax(uint64_t v)
 {
     if constexpr (W >= 1) {
-        const uint64_t o = xor_lanes<W>(v);
+        const uint64_t o = (uint64_t)__double_as_longlong(xor64<span_xor<W>()>(__longlong_as_double((long long)v)));
         return bfly_umax<W / 2>(o > v ? o : v);
     } else {
         return v;
@@ -221,7 +237,7 @@ template <int W>
 __device__ __forceinline__ uint32_t bfly_xor(uint32_t v)
 {
     if constexpr (W >= 1)
-        return bfly_xor<W / 2>(v ^ xor_lanes_u32<W>(v));
+        return bfly_xor<W / 2>(v ^ xor_any<span_xor<W>()>(v));
     else
         return v;
 }
@@ -368,15 +384,6 @@ __device__ __forceinline__ void select_smallest(const float *pm, int *slot, int 
         if (rank < keep)
             slot[seg * keep + rank] = me;
     }
-}
-
-// 64-bit value held by lane (lane ^ W)
-template <int W>
-__device__ __forceinline__ double xor64(double v)
-{
-    const uint64_t u = (uint64_t)__double_as_longlong(v);
-    const uint64_t r = ((uint64_t)xor_any<W>((uint32_t)(u >> 32)) << 32) | xor_any<W>((uint32_t)u);
-    return __longlong_as_double((long long)r);
 }
 
 // Bitonic half-cleaners with strides S, S/2, ..., 1 over lanes: the lower
