@@ -241,6 +241,10 @@ typedef struct rm_server_config {
     int max_batch;          /* requests per batch, 1..65536                             */
     int depth;              /* batches on the device at once, 1..4                      */
     int tile_frames;        /* requests per queue entry of a kernel, 1..64 (0 = 2)      */
+    int split;              /* waves sharing one request's P decoders: 1, 2 or 4 (0 = 4);
+                               the waves of a workgroup each run P/split decoders of the
+                               same request (Alg. 5 over all P is kept: the first
+                               minimum in decoder order wins), dividing its latency   */
 } rm_server_config;
 
 typedef struct rm_request {

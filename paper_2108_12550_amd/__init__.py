@@ -176,8 +176,9 @@ class Server:
     """Request server (rm_server_* of the C ABI): continuous batching of
     single-frame requests of any served code, P and L."""
 
-    def __init__(self, batch_bytes: int = 64 << 20, max_batch: int = 16384, depth: int = 2, tile_frames: int = 0):
-        self._h = rm_server_create(rm_server_config(batch_bytes, max_batch, depth, tile_frames))
+    def __init__(self, batch_bytes: int = 64 << 20, max_batch: int = 16384, depth: int = 2, tile_frames: int = 0,
+                 split: int = 0):
+        self._h = rm_server_create(rm_server_config(batch_bytes, max_batch, depth, tile_frames, split))
         if not self._h:
             raise RMError(-1, rm_last_error())
         self._keep = []  # device pools and decoders the requests refer to

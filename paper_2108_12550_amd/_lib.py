@@ -58,7 +58,7 @@ class rm_mixed_tuning(ctypes.Structure):
 
 class rm_server_config(ctypes.Structure):
     _fields_ = [("batch_bytes", ctypes.c_int64), ("max_batch", ctypes.c_int), ("depth", ctypes.c_int),
-                ("tile_frames", ctypes.c_int)]
+                ("tile_frames", ctypes.c_int), ("split", ctypes.c_int)]
 
 
 class rm_request(ctypes.Structure):

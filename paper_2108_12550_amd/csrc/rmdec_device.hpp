@@ -1112,29 +1112,44 @@ __device__ __forceinline__ RootRes<M, R, L, D> decode_root(const Ctx<M, R, L, D>
 
 // ---------------------------------------------------------------------------
 // One frame: the P decoders of Alg. 5, then the winner back in channel order.
-// The frame's N channel LLRs are read from `src`; the codeword goes to `ob`
-// (N/8 bytes) and the final metric to `opm` (if not null).  The calling
-// wavefront owns the LDS slice at `slice`; `lane` is its lane id.  From
-// `args` only the decoder set (maps, P, mode) is used.
+// decode_decoders runs decoders [d_begin, d_end) of the frame whose N channel
+// LLRs are at `src` and keeps, in decoder order, the first strictly smaller
+// final metric (Alg. 5); the winner's codeword masks stay in the LDS slice.
+// emit_codeword writes that codeword (N/8 bytes at `ob`) and the metric (to
+// `opm`, if not null).  The calling wavefront owns the LDS slice at `slice`;
+// `lane` is its lane id.  From `args` only the decoder set (maps, P, mode) is
+// used.
 // ---------------------------------------------------------------------------
+struct FrameBest {
+    float best;  // smallest final metric (+inf if no decoder ran)
+    int bestmap; // index of the map that takes the winner back to channel order
+};
+
 template <int M, int R, int L, int D>
-__device__ __forceinline__ void decode_frame(const KernelArgs &args, const float *src, uint8_t *ob, float *opm,
-                                             unsigned char *slice, int lane)
+__device__ __forceinline__ Ctx<M, R, L, D> frame_ctx(const KernelArgs &args, unsigned char *slice, int lane)
 {
     using Sh = Shape<M, R, L, D>;
-    constexpr int N = Sh::N;
     constexpr int G = Sh::G;
     Ctx<M, R, L, D> c;
     c.base = slice;
     c.lane = lane;
-    {
-        const int gw = c.lane / G;
-        c.g = gw % L;
-        c.gb = gw - c.g;
-        c.ds = gw / L;
-        c.lg = c.lane % G;
-    }
+    const int gw = lane / G;
+    c.g = gw % L;
+    c.gb = gw - c.g;
+    c.ds = gw / L;
+    c.lg = lane % G;
     c.pfht = args.pfht;
+    return c;
+}
+
+template <int M, int R, int L, int D>
+__device__ __forceinline__ FrameBest decode_decoders(const KernelArgs &args, const float *src, unsigned char *slice,
+                                                     int lane, int d_begin, int d_end)
+{
+    using Sh = Shape<M, R, L, D>;
+    constexpr int N = Sh::N;
+    constexpr int G = Sh::G;
+    const Ctx<M, R, L, D> c = frame_ctx<M, R, L, D>(args, slice, lane);
     wave_sync();
     for (int i = c.lane; i < N; i += kWave)
         c.y()[i] = src[i];
@@ -1143,12 +1158,12 @@ __device__ __forceinline__ void decode_frame(const KernelArgs &args, const float
     uint64_t *xb = c.xbest();
     if (c.lane < 2 * G)
         xb[c.lane] = 0ull;
-    for (int d0 = 0; d0 < args.P; d0 += D) {
-        // the maps of decoders d0 .. d0+D-1 (past P: a copy of the last, result unused)
+    for (int d0 = d_begin; d0 < d_end; d0 += D) {
+        // the maps of decoders d0 .. d0+D-1 (past d_end: a copy of the last, result unused)
         wave_sync();
 #pragma unroll
         for (int t = 0; t < D; t++) {
-            const int dd = d0 + t < args.P ? d0 + t : args.P - 1;
+            const int dd = d0 + t < d_end ? d0 + t : d_end - 1;
             // stored with columns and offset as byte offsets of float elements
             const uint4 *mg = (const uint4 *)(args.maps + (size_t)dd * args.maps_per_dec * kMapWords);
             uint4 *ml = (uint4 *)(c.maps_all() + t * Sh::MAPS_PER_DEC * kMapWords);
@@ -1160,7 +1175,7 @@ __device__ __forceinline__ void decode_frame(const KernelArgs &args, const float
         // Alg. 5 in decoder order: first minimum over the list, replace only if strictly smaller
 #pragma unroll
         for (int t = 0; t < D; t++) {
-            if (d0 + t >= args.P)
+            if (d0 + t >= d_end)
                 break;
             float pmin = from_lane(r.pm, (t * L) * G);
             int lstar = 0;
@@ -1183,8 +1198,20 @@ __device__ __forceinline__ void decode_frame(const KernelArgs &args, const float
         }
     }
     wave_sync();
+    return {best, bestmap};
+}
+
+template <int M, int R, int L, int D>
+__device__ __forceinline__ void emit_codeword(const KernelArgs &args, FrameBest fb, uint8_t *ob, float *opm,
+                                              unsigned char *slice, int lane)
+{
+    using Sh = Shape<M, R, L, D>;
+    constexpr int N = Sh::N;
+    constexpr int G = Sh::G;
+    const Ctx<M, R, L, D> c = frame_ctx<M, R, L, D>(args, slice, lane);
+    const uint64_t *xb = c.xbest();
     // the winner back in channel order, packed
-    const uint32_t *mi = args.maps + (size_t)bestmap * kMapWords;
+    const uint32_t *mi = args.maps + (size_t)fb.bestmap * kMapWords;
     uint32_t col[M + 1];
 #pragma unroll
     for (int k = 0; k < M; k++)
@@ -1219,8 +1246,16 @@ __device__ __forceinline__ void decode_frame(const KernelArgs &args, const float
         }
     }
     if (opm && c.lane == 0)
-        *opm = best;
+        *opm = fb.best;
     wave_sync();
+}
+
+template <int M, int R, int L, int D>
+__device__ __forceinline__ void decode_frame(const KernelArgs &args, const float *src, uint8_t *ob, float *opm,
+                                             unsigned char *slice, int lane)
+{
+    const FrameBest fb = decode_decoders<M, R, L, D>(args, src, slice, lane, 0, args.P);
+    emit_codeword<M, R, L, D>(args, fb, ob, opm, slice, lane);
 }
 
 // frame f of a contiguous batch
@@ -1385,6 +1420,67 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
         const KernelArgs ka = a.segs[tile.seg];
         int idx = 0;
         ((code == idx++ ? (serve_tile<Codes>(a, ka, tile, slice, lane), 0) : 0), ...);
+    }
+}
+
+// Serving launch with a request's decoders split over the waves of a
+// workgroup: the workgroup takes one queue entry at a time; for each request
+// wave w runs decoders [P*w/W, P*(w+1)/W) (W waves), the waves exchange their
+// best metrics through LDS, and the wave holding the first minimum in
+// decoder order writes the codeword -- the result of Alg. 5 over all P, with
+// the request's latency divided by about W.
+template <int WPE, class... Codes>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) rm_serve_split_kernel(ServeArgs a)
+{
+    __shared__ uint32_t s_tile;
+    __shared__ float s_best[4];
+    __shared__ int s_map[4];
+    const int W = (int)(blockDim.x / kWave);
+    while (true) {
+        if (threadIdx.x == 0)
+            s_tile = atomicAdd(a.head, 1u);
+        __syncthreads();
+        const uint32_t t = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_tile);
+        if (t >= a.n_tiles)
+            break; // the same entry for every wave: all leave together
+        const Tile tile = a.tiles[t];
+        const int code = a.seg_code[tile.seg];
+        const KernelArgs ka = a.segs[tile.seg];
+        for (uint32_t k = 0; k < tile.count; k++) {
+            uint32_t tid; // opaque per request: see rm_mixed_kernel
+            asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"(threadIdx.x));
+            const int lane = (int)(tid & (kWave - 1));
+            const int w = (int)(tid / kWave);
+            unsigned char *slice = rm_smem + w * MaxBytes<Codes...>::value;
+            const int d_begin = ka.P * w / W, d_end = ka.P * (w + 1) / W;
+            const Job j = a.jobs[tile.first + k];
+            FrameBest fb = {__builtin_inff(), 0};
+            int idx = 0;
+            ((code == idx++ ? (fb = decode_decoders<Codes::M, Codes::R, Codes::L, Codes::D>(ka, j.llr, slice, lane,
+                                                                                           d_begin, d_end),
+                               0)
+                            : 0),
+             ...);
+            if (lane == 0) {
+                s_best[w] = fb.best;
+                s_map[w] = fb.bestmap;
+            }
+            __syncthreads();
+            int win = 0;
+            for (int q = 1; q < W; q++)
+                win = s_best[q] < s_best[win] ? q : win;
+            if (w == win) {
+                const FrameBest wb = {s_best[win], s_map[win]};
+                idx = 0;
+                ((code == idx++ ? (emit_codeword<Codes::M, Codes::R, Codes::L, Codes::D>(
+                                       ka, wb, a.out_bits + (size_t)j.out * kServeBitsStride, a.out_pm + j.out, slice,
+                                       lane),
+                                   0)
+                                : 0),
+                 ...);
+            }
+            __syncthreads();
+        }
     }
 }
 

@@ -73,8 +73,8 @@ struct Batch {
 struct rm_server {
     rm_server_config cfg;
     int device = 0;
-    int waves = 2;
-    int grid_max[kGroups] = {0, 0, 0};
+    int waves = 2;                      // waves per block, one request per wave (split = 1)
+    int grid_max[kGroups] = {0, 0, 0};  // resident blocks of each serving kernel
     size_t off_segs = 0, off_codes = 0, off_jobs = 0, tab_bytes = 0, out_pm_off = 0;
     std::vector<Batch> batches;
     int open = -1;              // index of the open batch, or -1
@@ -231,8 +231,13 @@ int launch_open(rm_server *s)
         a.head = (uint32_t *)b.d_tab + g;
         a.out_bits = b.d_out;
         a.out_pm = (float *)(b.d_out + s->out_pm_off);
-        const int want = (g_count[g] + s->waves - 1) / s->waves;
-        e = group(g).launch(a, std::min(want, s->grid_max[g]), s->waves, st);
+        if (s->cfg.split > 1) {
+            // one queue entry per workgroup at a time, its requests split over the waves
+            e = group(g).launch_split(a, std::min(g_count[g], s->grid_max[g]), s->cfg.split, st);
+        } else {
+            const int want = (g_count[g] + s->waves - 1) / s->waves;
+            e = group(g).launch(a, std::min(want, s->grid_max[g]), s->waves, st);
+        }
         if (e == hipSuccess && g > 0)
             e = hipEventRecord(b.side_done[g - 1], st);
     }
@@ -301,10 +306,13 @@ rm_server *rm_server_create(const rm_server_config *cfg)
     rm_server_config c = *cfg;
     if (c.tile_frames == 0)
         c.tile_frames = 2;
+    if (c.split == 0)
+        c.split = 4;
     if (c.batch_bytes < 4096 || c.batch_bytes > ((int64_t)1 << 34) || c.max_batch < 1 || c.max_batch > 65536 ||
-        c.depth < 1 || c.depth > 4 || c.tile_frames < 1 || c.tile_frames > 64) {
+        c.depth < 1 || c.depth > 4 || c.tile_frames < 1 || c.tile_frames > 64 ||
+        (c.split != 1 && c.split != 2 && c.split != 4)) {
         fail(RM_E_INVAL, "config outside batch_bytes [4096, 2^34], max_batch [1, 65536], depth [1, 4], "
-                         "tile_frames [1, 64]");
+                         "tile_frames [1, 64], split in {1, 2, 4}");
         return nullptr;
     }
     rm_server *s = new (std::nothrow) rm_server();
@@ -322,10 +330,11 @@ rm_server *rm_server_create(const rm_server_config *cfg)
     int cus = 0;
     if (e == hipSuccess)
         e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device);
+    const int bw = c.split > 1 ? c.split : s->waves; // waves per block
     for (int g = 0; e == hipSuccess && g < kGroups; g++) {
         int per_cu = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, group(g).kernel, kWave * s->waves,
-                                                         (size_t)s->waves * group(g).lds_bytes_per_wave);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, c.split > 1 ? group(g).split_kernel : group(g).kernel,
+                                                         kWave * bw, (size_t)bw * group(g).lds_bytes_per_wave);
         s->grid_max[g] = std::max(1, per_cu * cus);
     }
     s->batches.resize((size_t)c.depth + 1);

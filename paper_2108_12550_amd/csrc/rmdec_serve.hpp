@@ -16,8 +16,10 @@ constexpr int kNumServeCodes = 5;
 struct ServeGroup {
     int L;                  // list size of every code in the kernel
     int lds_bytes_per_wave; // LDS slice of one wave
-    const void *kernel;     // for occupancy queries
+    const void *kernel;     // for occupancy queries (one wave per queue entry)
+    const void *split_kernel; // the same with a request's decoders split over a workgroup
     hipError_t (*launch)(const ServeArgs &a, int blocks, int waves, hipStream_t stream);
+    hipError_t (*launch_split)(const ServeArgs &a, int blocks, int waves, hipStream_t stream);
 };
 
 template <int WPE, int L>
@@ -26,13 +28,23 @@ struct ServeKernel {
     using C = Code<M, R, L, decoders_per_wave(M, L)>;
     using Slice = MaxBytes<C<7, 2>, C<8, 2>, C<9, 2>, C<10, 2>, C<8, 3>>;
     static const void *kernel() { return (const void *)&rm_serve_kernel<WPE, C<7, 2>, C<8, 2>, C<9, 2>, C<10, 2>, C<8, 3>>; }
+    static const void *split_kernel()
+    {
+        return (const void *)&rm_serve_split_kernel<WPE, C<7, 2>, C<8, 2>, C<9, 2>, C<10, 2>, C<8, 3>>;
+    }
     static hipError_t launch(const ServeArgs &a, int blocks, int waves, hipStream_t stream)
     {
         hipLaunchKernelGGL((rm_serve_kernel<WPE, C<7, 2>, C<8, 2>, C<9, 2>, C<10, 2>, C<8, 3>>), dim3(blocks),
                            dim3(kWave * waves), (size_t)waves * Slice::value, stream, a);
         return hipGetLastError();
     }
-    static ServeGroup group() { return ServeGroup{L, Slice::value, kernel(), &launch}; }
+    static hipError_t launch_split(const ServeArgs &a, int blocks, int waves, hipStream_t stream)
+    {
+        hipLaunchKernelGGL((rm_serve_split_kernel<WPE, C<7, 2>, C<8, 2>, C<9, 2>, C<10, 2>, C<8, 3>>), dim3(blocks),
+                           dim3(kWave * waves), (size_t)waves * Slice::value, stream, a);
+        return hipGetLastError();
+    }
+    static ServeGroup group() { return ServeGroup{L, Slice::value, kernel(), split_kernel(), &launch, &launch_split}; }
 };
 
 // index of (m, r) in kServeCodes, or -1

@@ -136,7 +136,8 @@ def test_server_null_and_invalid_calls():
     assert lib.rm_server_register_pool(None, None, 0) == _lib.RM_E_INVAL
     assert lib.rm_server_pending(None) == 0
     lib.rm_server_destroy(None)  # NULL-safe
-    for cfg in ((1024, 16, 2, 0), (1 << 20, 0, 2, 0), (1 << 20, 16, 5, 0), (1 << 20, 16, 2, 65)):
+    for cfg in ((1024, 16, 2, 0, 0), (1 << 20, 0, 2, 0, 0), (1 << 20, 16, 5, 0, 0), (1 << 20, 16, 2, 65, 0),
+                (1 << 20, 16, 2, 0, 3)):
         assert rmd.rm_server_create(rmd.rm_server_config(*cfg)) == 0
         assert "config" in rmd.rm_last_error()
     a, b = rmd.rm_server_now_us(), rmd.rm_server_now_us()
@@ -147,5 +148,5 @@ def test_server_create_without_device_fails_cleanly():
     import torch
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
-    assert rmd.rm_server_create(rmd.rm_server_config(1 << 20, 64, 2, 0)) == 0
+    assert rmd.rm_server_create(rmd.rm_server_config(1 << 20, 64, 2, 0, 0)) == 0
     assert "HIP" in rmd.rm_last_error()

@@ -126,12 +126,12 @@ def assert_same(got, ref, label):
     assert np.array_equal(gp, rp), f"{label}: metrics differ"
 
 
-@pytest.mark.parametrize("depth,tile", [(2, 0), (1, 1), (4, 8)])
-def test_mix_equals_alone(depth, tile):
-    print(f"case depth={depth} tile={tile}", flush=True)
+@pytest.mark.parametrize("depth,tile,split", [(2, 0, 0), (1, 1, 1), (4, 8, 2), (2, 3, 4), (3, 2, 1)])
+def test_mix_equals_alone(depth, tile, split):
+    print(f"case depth={depth} tile={tile} split={split}", flush=True)
     wl = Workload(1500, seed=depth * 10 + tile)
     ref = wl.reference()
-    srv = rmd.Server(batch_bytes=1 << 20, max_batch=512, depth=depth, tile_frames=tile)
+    srv = rmd.Server(batch_bytes=1 << 20, max_batch=512, depth=depth, tile_frames=tile, split=split)
     for k in wl.frames:
         srv.register_pool(wl.frames[k][1])
     rng = np.random.default_rng(5)
