@@ -74,6 +74,16 @@ def measured_traffic(path=TRAFFIC_FILE, sources=KERNEL_SOURCES):
         return None
 
 
+def fer_ci(errors: int, n: int, z: float = 1.96):
+    """Frame error rate with its Wilson score interval (95% for z = 1.96)."""
+    p = errors / n
+    den = 1 + z * z / n
+    mid = (p + z * z / (2 * n)) / den
+    half = z * np.sqrt(p * (1 - p) / n + z * z / (4 * n * n)) / den
+    return {"fer": float(p), "errors": int(errors), "frames": int(n),
+            "ci95": [float(max(0.0, mid - half)), float(min(1.0, mid + half))]}
+
+
 def cpu_baseline(llr_host: np.ndarray, gpu_bits: np.ndarray, budget_s: float, threads: int):
     """The CPU oracle on a bounded sample of the same frames."""
     import oracle
@@ -173,7 +183,7 @@ def main():
     fer = {}
     for k, e in enumerate(EBN0):
         xb = synth.unpack_bits(outs[k][0].cpu().numpy(), 1 << M)
-        fer[str(e)] = float(np.mean(np.any(xb != batches[k][0], axis=1)))
+        fer[str(e)] = fer_ci(int(np.any(xb != batches[k][0], axis=1).sum()), xb.shape[0])
     log(f"FER per Eb/N0: {fer}")
     dec_bits_30 = outs[EBN0.index(3.0)][0].cpu().numpy()
     llr_30 = batches[EBN0.index(3.0)][1]
@@ -312,7 +322,7 @@ def run_mixed(args):
         bb = b.cpu().numpy()
         gpu_bits[m] = bb
         same_sep &= bool(np.array_equal(bb, sb.cpu().numpy()) and torch.equal(p, sp))
-        fer[f"RM(2,{m})"] = float(np.mean(np.any(synth.unpack_bits(bb, 1 << m) != x, axis=1)))
+        fer[f"RM(2,{m})"] = fer_ci(int(np.any(synth.unpack_bits(bb, 1 << m) != x, axis=1).sum()), x.shape[0])
     log(f"FER per code: {fer}; fused == separate: {same_sep}")
 
     ops = sum(MIXED_OPS[m] for m, *_ in MIXED_CODES) * n
