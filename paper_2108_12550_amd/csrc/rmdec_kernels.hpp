@@ -38,9 +38,12 @@ constexpr int decoders_per_wave(int M, int L)
 {
     return L >= 8 ? 1 : (M >= 10 ? 4 : (M <= 8 && L == 4) ? 16 : 8) / L;
 }
-constexpr int waves_per_eu(int M, int L) { return M >= 10 && L >= 8 ? 2 : (M == 9 && L == 4) ? 4 : 3; }
+constexpr int waves_per_eu(int M, int R, int L)
+{
+    return M >= 10 && L >= 8 ? 2 : (M == 9 && R == 2 && L == 4) ? 4 : 3;
+}
 
-template <int M, int R, int L, int D = decoders_per_wave(M, L), int WPE = waves_per_eu(M, L)>
+template <int M, int R, int L, int D = decoders_per_wave(M, L), int WPE = waves_per_eu(M, R, L)>
 constexpr KernelEntry entry()
 {
     return KernelEntry{M, R, L, D, Shape<M, R, L, D>::BYTES, Shape<M, R, L, D>::MAPS_PER_DEC,
@@ -57,5 +60,7 @@ KernelTable kernels_codes_a();
 KernelTable kernels_codes_b();
 KernelTable kernels_codes_c();
 KernelTable kernels_codes_d();
+KernelTable kernels_codes_e();
+KernelTable kernels_codes_f();
 
 } // namespace rmdec

@@ -105,7 +105,21 @@ def test_leaf_roots(m, r, L):
     check(m, r, 2, L, PFHT, llr, seed=3)
 
 
+@pytest.mark.parametrize("m,r", [(9, 3), (9, 4), (8, 4)])
+@pytest.mark.parametrize("L", [1, 2, 4, 8])
+def test_higher_order_codes(m, r, L):
+    """RM(3,9), RM(4,9), RM(4,8): deeper permutation domains, more SPC leaves."""
+    _, llr = synth.frames(m, r, 60, 3.0, seed=500 + m * 10 + r)
+    check(m, r, 3, L, PFHT, llr, seed=L + 1)
+
+
+def test_table5_rm48_p16_l4():
+    _, llr = synth.frames(8, 4, 96, 3.5, seed=77)
+    check(8, 4, 16, 4, PFHT, llr, seed=2)
+
+
 @pytest.mark.parametrize("m,r,L", [(7, 2, 2), (7, 2, 4), (9, 2, 4), (9, 2, 8), (8, 3, 4), (8, 3, 8), (10, 2, 4),
+                                   (9, 3, 4), (9, 4, 8),
                                    (5, 2, 8), (6, 1, 4), (4, 3, 4)])
 def test_plain_list_mode(m, r, L):
     """FHT-FSCL-L without permutations: one active path at the start."""

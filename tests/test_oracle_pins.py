@@ -384,3 +384,20 @@ def test_fer_matches_fig5(name, mode, L, ebn0, n):
     k = _fer(9, 2, 1, L, mode, float(ebn0), n, seed=31)
     lo, hi = wilson(k, n, 3.29)  # 99.9% interval
     assert lo <= pub <= hi, (name, ebn0, k / n, pub)
+
+
+@pytest.mark.parametrize("key,m,r,name,mode,L,ebn0,n", [
+    ("fer_rm39", 9, 3, "FHT-FSCL-1", oracle.PERM_NONE, 1, "3.0", 3000),
+    ("fer_rm39", 9, 3, "FHT-FSCL-4", oracle.PERM_NONE, 4, "3.0", 5000),
+    ("fer_rm39", 9, 3, "p-FHT-FSCL-4", oracle.PERM_PFHT, 4, "2.5", 5000),
+    ("fer_rm49", 9, 4, "FHT-FSCL-4", oracle.PERM_NONE, 4, "4.0", 12000),
+    ("fer_rm49", 9, 4, "p-FHT-FSC-2", oracle.PERM_PFHT, 2, "3.5", 5000),
+    ("fer_rm49", 9, 4, "p-FHT-FSCL-4", oracle.PERM_PFHT, 4, "3.5", 12000),
+])
+def test_fer_matches_fig5_higher_orders(key, m, r, name, mode, L, ebn0, n):
+    """RM(3,9) and RM(4,9) against Fig. 5(b) and 5(c): deeper permutation
+    domains and many SPC leaves (99.9% Wilson intervals)."""
+    pub = GOLDEN[key][name][ebn0]
+    k = _fer(m, r, 1, L, mode, float(ebn0), n, seed=47)
+    lo, hi = wilson(k, n, 3.29)
+    assert lo <= pub <= hi, (key, name, ebn0, k / n, pub)
