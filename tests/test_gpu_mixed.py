@@ -204,3 +204,31 @@ def test_autotuned_launch_equals_per_code():
     bufs = dev_buffers(segs)
     mx.decode(seg_list(decs, segs, bufs, tune["tile_frames"]), stream=stream)
     assert_same(fetch(bufs), ref, "autotuned launch")
+
+
+def test_full_size_mixed_graph_sampled():
+    """The benchmark's fused launch at full size: 262,144 frames of each code
+    (1,048,576 in one launch, Eb/N0 ~ U[2,4] per frame), replayed from its
+    graph; every frame is a codeword and sampled frames match the oracle."""
+    n = 262144
+    decs = decoders()
+    segs = make_inputs((n, n, n, n), seed=1234)
+    bufs = dev_buffers(segs)
+    mx = rmd.MixedLauncher(max_tiles=4 * n + 16)
+    stream = torch.cuda.Stream()
+    mx.capture(seg_list(decs, segs, bufs, (1, 8, 4, 1)), stream)
+    mx.replay()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5)
+    for (m, P, s, llr), (_, b, p) in zip(segs, bufs):
+        print(f"case full-size mixed RM(2,{m})", flush=True)
+        h = torch.from_numpy(synth.monomial_table(m, m - 3).astype(np.float32)).cuda()
+        for c in range(0, n, 65536):
+            xb = torch.from_numpy(synth.unpack_bits(b[c:c + 65536].cpu().numpy(), 1 << m).astype(np.float32)).cuda()
+            assert int(torch.remainder(xb @ h.T, 2.0).sum().item()) == 0
+        idx = np.sort(rng.choice(n, 12, replace=False))
+        rb, rp = oracle.OracleDecoder(m, 2, P, 4, seed=s).decode_batch(np.ascontiguousarray(llr[idx]),
+                                                                     n_threads=THREADS)
+        assert np.array_equal(b.cpu().numpy()[idx], rb), f"RM(2,{m})"
+        assert np.max(np.abs(p.cpu().numpy()[idx] - rp) / np.maximum(1.0, np.abs(rp))) <= 1e-5
+    mx.close()

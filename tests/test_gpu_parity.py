@@ -201,3 +201,28 @@ def test_full_size_rm29_p20_l4_sampled():
     idx = np.sort(rng.choice(n, 48, replace=False))
     rb, rp = oracle_decode(9, 2, 20, 4, 0, PFHT, llr[idx])
     assert_parity((bits[idx], pm[idx]), (rb, rp), "full-size sample")
+
+
+def _full_size_check(m, r, P, L, n, ebn0, seed, samples, label):
+    _, llr = synth.frames(m, r, n, ebn0, seed=seed)
+    print(f"case full-size {label} n={n}", flush=True)
+    bits, pm = gpu_decode(m, r, P, L, 0, PFHT, llr)
+    h = torch.from_numpy(synth.monomial_table(m, m - r - 1).astype(np.float32)).cuda()
+    for c in range(0, n, 65536):  # syndrome of every frame against the dual code
+        xb = torch.from_numpy(synth.unpack_bits(bits[c:c + 65536], 1 << m).astype(np.float32)).cuda()
+        assert int(torch.remainder(xb @ h.T, 2.0).sum().item()) == 0
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(n, samples, replace=False))
+    rb, rp = oracle_decode(m, r, P, L, 0, PFHT, llr[idx])
+    assert_parity((bits[idx], pm[idx]), (rb, rp), f"full-size {label} sample")
+
+
+def test_full_size_rm29_p512_l1_sampled():
+    """The comparison point RM(2,9) with 512 permuted decoders at L = 1,
+    131,072 frames in one launch."""
+    _full_size_check(9, 2, 512, 1, 131072, 2.5, 3, 24, "RM(2,9) P=512 L=1")
+
+
+def test_full_size_rm38_p8_l8_sampled():
+    """RM(3,8) with 8 permuted decoders at L = 8, 131,072 frames in one launch."""
+    _full_size_check(8, 3, 8, 8, 131072, 2.5, 4, 48, "RM(3,8) P=8 L=8")
