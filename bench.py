@@ -84,17 +84,17 @@ def fer_ci(errors: int, n: int, z: float = 1.96):
             "ci95": [float(max(0.0, mid - half)), float(min(1.0, mid + half))]}
 
 
-def cpu_baseline(llr_host: np.ndarray, gpu_bits: np.ndarray, budget_s: float, threads: int):
+def cpu_baseline(llr_host: np.ndarray, gpu_bits: np.ndarray, budget_s: float, threads: int, perm_mode: int = 1):
     """The CPU oracle on a bounded sample of the same frames."""
     import oracle
-    od = oracle.OracleDecoder(M, R, P, L, seed=SEED)
+    od = oracle.OracleDecoder(M, R, P, L, seed=SEED, perm_mode=perm_mode)
     chunk = 64 * threads
     done = 0
     t0 = time.perf_counter()
     same = True
     while done < llr_host.shape[0] and time.perf_counter() - t0 < budget_s:
         sl = slice(done, min(done + chunk, llr_host.shape[0]))
-        bits, _ = od.decode_batch(llr_host[sl], n_threads=threads)
+        bits, _ = od.decode_batch(llr_host[sl], n_threads=threads, frame0=sl.start)
         same &= bool(np.array_equal(bits, gpu_bits[sl]))
         done = sl.stop
     dt = time.perf_counter() - t0
@@ -116,6 +116,8 @@ def main():
     ap.add_argument("--workload", choices=("rm29", "mixed", "serve"), default="rm29")
     ap.add_argument("--serve-ms", type=float, default=100.0, help="arrival window per rate of the serving trace")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving section of the rm29 workload")
+    ap.add_argument("--fresh", action="store_true",
+                    help="rm29 workload with maps drawn afresh for every frame (the draw is timed with the decode)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -144,7 +146,8 @@ def main():
         batches.append((x, llr, torch.from_numpy(llr).to(dev)))
     log(f"inputs ready in {time.perf_counter() - t0:.1f} s")
 
-    dec = rmd.Decoder(M, R, P, L, seed=SEED)
+    mode = rmd.RM_PERM_FRESH if args.fresh else rmd.RM_PERM_PFHT
+    dec = rmd.Decoder(M, R, P, L, seed=SEED, perm_mode=mode)
     stream = torch.cuda.Stream(device=dev)
     outs = [(torch.empty((n, 64), dtype=torch.uint8, device=dev), torch.empty((n,), dtype=torch.float32, device=dev))
             for _ in EBN0]
@@ -191,8 +194,9 @@ def main():
     ops_per_launch = OPS_PER_FRAME * n
     achieved = ops_per_launch / (ms_per_step / 1e3) / 1e12
     roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(ALU_PEAK_TOPS, 4), "unit": "TFLOP/s",
-            "frac": round(achieved / ALU_PEAK_TOPS, 5), "traffic": measured_traffic(),
-            "kernel": KERNEL_NAME, "avg_launch_ms": round(ms_per_step, 4),
+            "frac": round(achieved / ALU_PEAK_TOPS, 5), "traffic": None if args.fresh else measured_traffic(),
+            "kernel": KERNEL_NAME + (" + rm_fresh_maps_kernel" if args.fresh else ""),
+            "avg_launch_ms": round(ms_per_step, 4),
             "hbm_gbs_algorithmic": round((4 * 512 + 64 + 4) * fps / 1e9, 2)}
 
     serving = None
@@ -204,7 +208,7 @@ def main():
     if not args.no_cpu_baseline:
         gpu_bits = dec_bits_30
         threads = min(16, os.cpu_count() or 1)
-        cpu, same = cpu_baseline(llr_30, gpu_bits, args.cpu_budget, threads)
+        cpu, same = cpu_baseline(llr_30, gpu_bits, args.cpu_budget, threads, perm_mode=mode)
         log(f"cpu_baseline: {cpu}")
 
     out = {
@@ -212,7 +216,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"RM(9,2) N=512 K=46 (paper's RM(2,9)), P=20 permuted decoders, L=4, "
-                               f"p-FHT-FSCL, BPSK/AWGN Eb/N0 2.0-4.0 dB step 0.5",
+                               f"p-FHT-FSCL{' with per-frame fresh maps' if args.fresh else ''}, "
+                               f"BPSK/AWGN Eb/N0 2.0-4.0 dB step 0.5",
                    "frames_per_step": n, "ebn0_db": EBN0, "seed": SEED},
         "info_gbit_s": round(fps * K / 1e9, 4),
         "wall_s_timed": round(wall, 3),

@@ -44,6 +44,12 @@ extern "C" {
 #define RM_PERM_NONE 0 /* FHT-FSCL: identity, no permutation domain; the list starts
                           from one path, the other L-1 entries inactive            */
 #define RM_PERM_PFHT 1 /* p-FHT-FSCL: random affine permutations (Alg. 2)         */
+#define RM_PERM_FRESH 2 /* p-FHT-FSCL with maps drawn afresh for every frame: the
+                           initialisation of Alg. 2 applied per received vector.
+                           Frame f of a call (f = 0, 1, ...) decodes with the maps
+                           of rm_perm_tables_frame(..., frame = f, ...); the draw
+                           runs on the device, chunk by chunk, inside
+                           rm_decode_batch (results depend on f)                  */
 
 typedef struct rm_decoder rm_decoder;
 
@@ -53,7 +59,7 @@ typedef struct rm_config {
     int P;               /* parallel decoders per frame (paper's M), 1..1024      */
     int L;               /* list size per decoder: 1, 2, 4 or 8                   */
     uint64_t seed;       /* seed of the permutation draw (SplitMix64)             */
-    int perm_mode;       /* RM_PERM_PFHT or RM_PERM_NONE                          */
+    int perm_mode;       /* RM_PERM_PFHT, RM_PERM_NONE or RM_PERM_FRESH           */
     int waves_per_block; /* 0 = library choice; else 1..4 wavefronts per block   */
 } rm_config;
 
@@ -92,7 +98,8 @@ rm_decoder *rm_decoder_create_ex(const rm_config *cfg);
  *   out_metric device, n_frames float32 final path metrics, or NULL.
  * Work is queued on the decoder's stream (rm_decoder_set_stream; default the
  * null stream) and the call returns without waiting.  n_frames = 0 is a
- * no-op.  Results depend only on (m, r, P, L, seed, perm_mode, llr).
+ * no-op.  Results depend only on (m, r, P, L, seed, perm_mode, llr), and in
+ * RM_PERM_FRESH mode also on each frame's index within the call.
  */
 int rm_decode_batch(rm_decoder *d, const float *llr, int64_t n_frames, uint8_t *out_bits, float *out_metric);
 
@@ -115,6 +122,18 @@ int rm_decoder_info(const rm_decoder *d, rm_info *out);
  */
 int rm_perm_tables(int m, int r, int P, int L, uint64_t seed, int perm_mode, uint16_t *rows, uint16_t *b,
                    int *mdim, int cap);
+
+/*
+ * Host only: as rm_perm_tables, for frame `frame` (0 <= frame < 2^43) of a
+ * call.  In RM_PERM_FRESH mode decoder d of frame f draws, in the order of
+ * rm_decoder_create, from the SplitMix64 generator whose state is the first
+ * output of the generator seeded with seed ^ (f << 20 | d); each map builds
+ * A row by row (row k: low bits of one output, redrawn until it lies outside
+ * the span of rows 0..k-1; again uniform over invertible A), then b.  The
+ * other modes ignore `frame`.
+ */
+int rm_perm_tables_frame(int m, int r, int P, int L, uint64_t seed, int perm_mode, int64_t frame, uint16_t *rows,
+                         uint16_t *b, int *mdim, int cap);
 
 /* 1 if a kernel is built for (m, r, L, perm_mode), else 0.  Host only. */
 int rm_supported(int m, int r, int L, int perm_mode);

@@ -18,6 +18,7 @@ _LIB = os.path.join(_HERE, "librmoracle.so")
 
 PERM_NONE = 0
 PERM_PFHT = 1
+PERM_FRESH = 2
 
 NODE_INTERNAL, NODE_PERM, NODE_FHTL, NODE_SPCL = 0, 1, 2, 3
 NODE_NAMES = {NODE_INTERNAL: "internal", NODE_PERM: "perm", NODE_FHTL: "fhtl", NODE_SPCL: "spcl"}
@@ -46,8 +47,12 @@ def lib():
         L.rmo_create.argtypes = [ctypes.c_int] * 5 + [ctypes.c_uint64]
         L.rmo_destroy.argtypes = [ctypes.c_void_p]
         L.rmo_decode.argtypes = [ctypes.c_void_p, P(ctypes.c_float), P(ctypes.c_uint8), P(ctypes.c_float)]
+        L.rmo_decode_frame.argtypes = [ctypes.c_void_p, P(ctypes.c_float), ctypes.c_int64, P(ctypes.c_uint8),
+                                       P(ctypes.c_float)]
         L.rmo_decode_batch.argtypes = [ctypes.c_void_p, P(ctypes.c_float), ctypes.c_int64, P(ctypes.c_uint8),
                                        P(ctypes.c_float), ctypes.c_int]
+        L.rmo_decode_batch_at.argtypes = [ctypes.c_void_p, P(ctypes.c_float), ctypes.c_int64, ctypes.c_int64,
+                                          P(ctypes.c_uint8), P(ctypes.c_float), ctypes.c_int]
         L.rmo_info_set.argtypes = [ctypes.c_int, ctypes.c_int, P(ctypes.c_uint8)]
         L.rmo_encode.argtypes = [ctypes.c_int, P(ctypes.c_uint8), P(ctypes.c_uint8)]
         L.rmo_fht.argtypes = [ctypes.c_int, ctypes.c_int, P(ctypes.c_float), ctypes.c_float, P(ctypes.c_uint8),
@@ -59,6 +64,8 @@ def lib():
         L.rmo_perm_count.argtypes = [ctypes.c_void_p]
         L.rmo_perm_export.argtypes = [ctypes.c_void_p, P(ctypes.c_uint16), P(ctypes.c_uint16), P(ctypes.c_int),
                                       ctypes.c_int]
+        L.rmo_perm_export_frame.argtypes = [ctypes.c_void_p, ctypes.c_int64, P(ctypes.c_uint16), P(ctypes.c_uint16),
+                                            P(ctypes.c_int), ctypes.c_int]
         L.rmo_splitmix64_next.restype = ctypes.c_uint64
         L.rmo_splitmix64_next.argtypes = [P(ctypes.c_uint64)]
         _lib = L
@@ -85,33 +92,38 @@ class OracleDecoder:
             lib().rmo_destroy(h)
             self._h = None
 
-    def decode(self, y: np.ndarray):
+    def decode(self, y: np.ndarray, frame: int = 0):
+        """Decode one frame; `frame` is its index (it keys the maps of the fresh mode)."""
         y = np.ascontiguousarray(y, dtype=np.float32)
         x = np.zeros(self.N, dtype=np.uint8)
         pm = np.zeros(1, dtype=np.float32)
-        lib().rmo_decode(self._h, _p(y, ctypes.c_float), _p(x, ctypes.c_uint8), _p(pm, ctypes.c_float))
+        lib().rmo_decode_frame(self._h, _p(y, ctypes.c_float), int(frame), _p(x, ctypes.c_uint8),
+                               _p(pm, ctypes.c_float))
         return x, float(pm[0])
 
-    def decode_batch(self, llr: np.ndarray, n_threads: int = 1):
-        """llr: (n_frames, N) float32.  Returns packed bits (n, N/8) uint8 and metrics (n,)."""
+    def decode_batch(self, llr: np.ndarray, n_threads: int = 1, frame0: int = 0):
+        """llr: (n_frames, N) float32, frames numbered frame0, frame0+1, ...
+        Returns packed bits (n, N/8) uint8 and metrics (n,)."""
         llr = np.ascontiguousarray(llr, dtype=np.float32).reshape(-1, self.N)
         n = llr.shape[0]
         bits = np.zeros((n, self.N // 8), dtype=np.uint8)
         pm = np.zeros(n, dtype=np.float32)
-        rc = lib().rmo_decode_batch(self._h, _p(llr, ctypes.c_float), n, _p(bits, ctypes.c_uint8),
-                                    _p(pm, ctypes.c_float), int(n_threads))
+        rc = lib().rmo_decode_batch_at(self._h, _p(llr, ctypes.c_float), n, int(frame0),
+                                       _p(bits, ctypes.c_uint8), _p(pm, ctypes.c_float), int(n_threads))
         if rc != 0:
             raise RuntimeError("oracle batch decode failed")
         return bits, pm
 
-    def perms(self):
-        """All drawn affine maps in draw order: list of (rows[m], b)."""
+    def perms(self, frame: int = 0):
+        """All drawn affine maps in draw order: list of (rows[m], b) (in the
+        fresh mode, those of frame `frame`)."""
         L = lib()
         k = L.rmo_perm_count(self._h)
         rows = np.zeros(k * 16, dtype=np.uint16)
         b = np.zeros(k, dtype=np.uint16)
         md = np.zeros(k, dtype=np.int32)
-        got = L.rmo_perm_export(self._h, _p(rows, ctypes.c_uint16), _p(b, ctypes.c_uint16), _p(md, ctypes.c_int), k)
+        got = L.rmo_perm_export_frame(self._h, int(frame), _p(rows, ctypes.c_uint16), _p(b, ctypes.c_uint16),
+                                      _p(md, ctypes.c_int), k)
         assert got == k
         return [(rows[i * 16:i * 16 + md[i]].copy(), int(b[i])) for i in range(k)]
 

@@ -113,6 +113,47 @@ static void amap_draw(amap *a, int m, uint64_t *st)
     a->b = (uint32_t)(rmo_splitmix64_next(st) & mask);
 }
 
+/* Do the n rows (m columns) have rank n?  Gaussian elimination over GF(2). */
+static int gf2_rows_independent(const uint32_t *rows, int n, int m)
+{
+    uint32_t t[MAXM];
+    memcpy(t, rows, (size_t)n * sizeof *t);
+    int rank = 0;
+    for (int col = 0; col < m && rank < n; col++) {
+        int piv = -1;
+        for (int k = rank; k < n; k++)
+            if ((t[k] >> col) & 1u) {
+                piv = k;
+                break;
+            }
+        if (piv < 0)
+            continue;
+        uint32_t tmp = t[piv];
+        t[piv] = t[rank];
+        t[rank] = tmp;
+        for (int k = 0; k < n; k++)
+            if (k != rank && ((t[k] >> col) & 1u))
+                t[k] ^= t[rank];
+        rank++;
+    }
+    return rank == n;
+}
+
+/* The fresh mode's draw of one uniform element of AGL(m,2), built row by
+ * row: row k of A is drawn (low m bits of one SplitMix64 output) until rows
+ * 0..k are linearly independent, so every ordered basis of F2^m, hence every
+ * invertible A, is equally likely; then b. */
+static void amap_draw_rowwise(amap *a, int m, uint64_t *st)
+{
+    const uint32_t mask = (1u << m) - 1u;
+    a->m = m;
+    for (int k = 0; k < m; k++)
+        do
+            a->row[k] = (uint32_t)(rmo_splitmix64_next(st) & mask);
+        while (!gf2_rows_independent(a->row, k + 1, m));
+    a->b = (uint32_t)(rmo_splitmix64_next(st) & mask);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Code construction (Section II-A): x = u G^{(x)m}, G = [[1,0],[1,1]];      */
 /* u_i is frozen iff the weight w_i of row i of G^{(x)m} is below            */
@@ -478,17 +519,38 @@ int rmo_spcl(int s, int L, const float *alpha, const float *pm_in, uint8_t *x, f
 /* ------------------------------------------------------------------------ */
 struct rmo_decoder {
     int m, r, P, L, mode;
+    uint64_t seed;
     int n_perm_nodes; /* internal nodes visited while isPermutation holds */
     amap *init;       /* [P][L] */
     amap *cand;       /* [P][n_perm_nodes][2L] */
 };
+
+/* Draw one decoder's maps for one frame of the fresh mode from the stream
+ * st: the L initial maps, then 2L candidate maps for every
+ * permutation-domain node in preorder, each built row by row. */
+static void draw_decoder_maps(int m, int L, int nperm, uint64_t *st, amap *init, amap *cand)
+{
+    for (int l = 0; l < L; l++)
+        amap_draw_rowwise(&init[l], m, st);
+    for (int v = 0; v < nperm; v++)
+        for (int c = 0; c < 2 * L; c++)
+            amap_draw_rowwise(&cand[(size_t)v * 2 * L + c], m - v, st);
+}
+
+/* Stream of decoder dd for frame f in the fresh mode: one SplitMix64 step
+ * from seed ^ (f << 20 | dd) gives the starting state. */
+static uint64_t fresh_stream(uint64_t seed, int64_t f, int dd)
+{
+    uint64_t st = seed ^ (((uint64_t)f << 20) | (uint64_t)dd);
+    return rmo_splitmix64_next(&st);
+}
 
 /* The permutation domain covers the internal nodes reached from the root by
  * left steps before the first first-order node (Alg. 2: isPermutation is set
  * at the root and cleared at the first r = 1 node, which is the leftmost). */
 static int count_perm_nodes(int m, int r, int mode)
 {
-    if (mode != RMO_PERM_PFHT)
+    if (mode == RMO_PERM_NONE)
         return 0;
     int c = 0;
     while (1 < r && r < m - 1) {
@@ -503,7 +565,9 @@ rmo_decoder *rmo_create(int m, int r, int P, int L, int perm_mode, uint64_t seed
 {
     if (m < 2 || m > MAXM || r < 1 || r > m - 1 || P < 1 || L < 1 || L > MAXL)
         return NULL;
-    if (perm_mode != RMO_PERM_NONE && perm_mode != RMO_PERM_PFHT)
+    if (perm_mode != RMO_PERM_NONE && perm_mode != RMO_PERM_PFHT && perm_mode != RMO_PERM_FRESH)
+        return NULL;
+    if (perm_mode == RMO_PERM_FRESH && P > (1 << 20))
         return NULL;
     rmo_decoder *d = calloc(1, sizeof *d);
     d->m = m;
@@ -511,6 +575,7 @@ rmo_decoder *rmo_create(int m, int r, int P, int L, int perm_mode, uint64_t seed
     d->P = P;
     d->L = L;
     d->mode = perm_mode;
+    d->seed = seed;
     d->n_perm_nodes = count_perm_nodes(m, r, perm_mode);
     d->init = calloc((size_t)P * L, sizeof *d->init);
     d->cand = calloc((size_t)P * (d->n_perm_nodes ? d->n_perm_nodes : 1) * 2 * L, sizeof *d->cand);
@@ -519,7 +584,7 @@ rmo_decoder *rmo_create(int m, int r, int P, int L, int perm_mode, uint64_t seed
     for (int p = 0; p < P; p++) {
         for (int l = 0; l < L; l++) {
             amap *a = &d->init[(size_t)p * L + l];
-            if (perm_mode == RMO_PERM_PFHT) {
+            if (perm_mode != RMO_PERM_NONE) {
                 amap_draw(a, m, &st);
             } else { /* identity */
                 a->m = m;
@@ -575,6 +640,35 @@ int rmo_perm_export(const rmo_decoder *d, uint16_t *rows, uint16_t *b, int *mdim
     return k;
 }
 
+int rmo_perm_export_frame(const rmo_decoder *d, int64_t frame, uint16_t *rows, uint16_t *b, int *mdim, int cap)
+{
+    if (d->mode != RMO_PERM_FRESH)
+        return rmo_perm_export(d, rows, b, mdim, cap);
+    const int L = d->L, nperm = d->n_perm_nodes;
+    amap *init = calloc((size_t)L, sizeof *init);
+    amap *cand = calloc((size_t)(nperm ? nperm : 1) * 2 * L, sizeof *cand);
+    int k = 0;
+    for (int p = 0; p < d->P && k >= 0; p++) {
+        uint64_t st = fresh_stream(d->seed, frame, p);
+        draw_decoder_maps(d->m, L, nperm, &st, init, cand);
+        for (int q = 0; q < L + nperm * 2 * L && k >= 0; q++) {
+            const amap *a = q < L ? &init[q] : &cand[q - L];
+            if (k >= cap) {
+                k = -1;
+                break;
+            }
+            for (int j = 0; j < 16; j++)
+                rows[k * 16 + j] = (uint16_t)(j < a->m ? a->row[j] : 0);
+            b[k] = (uint16_t)a->b;
+            mdim[k] = a->m;
+            k++;
+        }
+    }
+    free(init);
+    free(cand);
+    return k;
+}
+
 /* Preorder node list as (kind, r, m) triples, following Alg. 2's tests in
  * their order: 1<r<m-1 internal, then r=1 FHTL, then r=m-1 SPCL. */
 static int sched_walk(int m, int r, int *is_perm, int *out, int cap, int k)
@@ -624,9 +718,9 @@ int rmo_schedule(int m, int r, int perm_mode, int *out, int cap)
 /* ------------------------------------------------------------------------ */
 typedef struct {
     const rmo_decoder *dec;
-    int d;         /* which of the M parallel decoders (Alg. 5) */
-    int is_perm;   /* isPermutation */
-    int perm_node; /* index of the next permutation-domain node */
+    const amap *cand; /* this decoder's candidate maps: [n_perm_nodes][2L] */
+    int is_perm;      /* isPermutation */
+    int perm_node;    /* index of the next permutation-domain node */
 } ctx_t;
 
 static float **alloc_fvecs(int L, int n)
@@ -673,7 +767,7 @@ static void node_decode(ctx_t *c, int r, int m, float *const *alpha, const float
             /* Permutation domain: 2L candidates, candidate cc permutes the LLRs
              * of path cc mod L; LM = sum |f(permuted)|; keep the L largest. */
             is_per = 1;
-            cands = &c->dec->cand[((size_t)c->d * c->dec->n_perm_nodes + c->perm_node) * 2 * L];
+            cands = &c->cand[(size_t)c->perm_node * 2 * L];
             c->perm_node++;
             float lm[2 * MAXL];
             float *t = malloc((size_t)n * sizeof *t);
@@ -765,6 +859,11 @@ static void node_decode(ctx_t *c, int r, int m, float *const *alpha, const float
 /* ------------------------------------------------------------------------ */
 int rmo_decode(const rmo_decoder *d, const float *y, uint8_t *xhat, float *pm)
 {
+    return rmo_decode_frame(d, y, 0, xhat, pm);
+}
+
+int rmo_decode_frame(const rmo_decoder *d, const float *y, int64_t frame, uint8_t *xhat, float *pm)
+{
     const int m = d->m, L = d->L, n = 1 << m;
     float best = INFINITY;
     memset(xhat, 0, (size_t)n);
@@ -773,9 +872,20 @@ int rmo_decode(const rmo_decoder *d, const float *y, uint8_t *xhat, float *pm)
     uint8_t *xo = malloc((size_t)n);
     float pm0[MAXL], pmo[MAXL];
     int anc[MAXL];
+    const int fresh = d->mode == RMO_PERM_FRESH;
+    amap *finit = fresh ? calloc((size_t)L, sizeof *finit) : NULL;
+    amap *fcand = fresh ? calloc((size_t)(d->n_perm_nodes ? d->n_perm_nodes : 1) * 2 * L, sizeof *fcand) : NULL;
     for (int p = 0; p < d->P; p++) {
+        const amap *init = &d->init[(size_t)p * L];
+        const amap *cand = &d->cand[(size_t)p * d->n_perm_nodes * 2 * L];
+        if (fresh) { /* this frame's own maps for decoder p */
+            uint64_t st = fresh_stream(d->seed, frame, p);
+            draw_decoder_maps(m, L, d->n_perm_nodes, &st, finit, fcand);
+            init = finit;
+            cand = fcand;
+        }
         for (int l = 0; l < L; l++) {
-            const amap *ai = &d->init[(size_t)p * L + l];
+            const amap *ai = &init[l];
             for (int i = 0; i < n; i++)
                 a[l][i] = y[amap_apply(ai, (uint32_t)i)];
             /* Alg. 2 starts its L paths from L different permutations.
@@ -783,9 +893,9 @@ int rmo_decode(const rmo_decoder *d, const float *y, uint8_t *xhat, float *pm)
              * entries 1..L-1 begin inactive, with an infinite metric, so
              * they never displace a finite candidate and the list fills
              * through the path splits alone. */
-            pm0[l] = (d->mode == RMO_PERM_PFHT || l == 0) ? 0.0f : INFINITY;
+            pm0[l] = (d->mode != RMO_PERM_NONE || l == 0) ? 0.0f : INFINITY;
         }
-        ctx_t c = {d, p, d->mode == RMO_PERM_PFHT, 0};
+        ctx_t c = {d, cand, d->mode != RMO_PERM_NONE, 0};
         node_decode(&c, d->r, m, a, pm0, x, pmo, anc);
         int ls = 0;
         for (int l = 1; l < L; l++)
@@ -793,7 +903,7 @@ int rmo_decode(const rmo_decoder *d, const float *y, uint8_t *xhat, float *pm)
                 ls = l;
         if (pmo[ls] < best) {
             best = pmo[ls];
-            const amap *ai = &d->init[(size_t)p * L + anc[ls]];
+            const amap *ai = &init[anc[ls]];
             for (int i = 0; i < n; i++)
                 xo[amap_apply(ai, (uint32_t)i)] = x[ls][i];
             memcpy(xhat, xo, (size_t)n);
@@ -803,13 +913,15 @@ int rmo_decode(const rmo_decoder *d, const float *y, uint8_t *xhat, float *pm)
     free_vecs((void **)a, L);
     free_vecs((void **)x, L);
     free(xo);
+    free(finit);
+    free(fcand);
     return 0;
 }
 
 typedef struct {
     const rmo_decoder *d;
     const float *llr;
-    int64_t f0, f1;
+    int64_t f0, f1, frame0;
     uint8_t *out_bits;
     float *out_pm;
 } job_t;
@@ -821,7 +933,7 @@ static void *batch_worker(void *arg)
     uint8_t *x = malloc((size_t)n);
     for (int64_t f = j->f0; f < j->f1; f++) {
         float pm;
-        rmo_decode(j->d, j->llr + f * n, x, &pm);
+        rmo_decode_frame(j->d, j->llr + f * n, j->frame0 + f, x, &pm);
         uint8_t *ob = j->out_bits + f * (n / 8);
         memset(ob, 0, (size_t)n / 8);
         for (int i = 0; i < n; i++)
@@ -836,7 +948,13 @@ static void *batch_worker(void *arg)
 int rmo_decode_batch(const rmo_decoder *d, const float *llr, int64_t n_frames, uint8_t *out_bits, float *out_pm,
                      int n_threads)
 {
-    if (!d || n_frames < 0 || (1 << d->m) < 8)
+    return rmo_decode_batch_at(d, llr, n_frames, 0, out_bits, out_pm, n_threads);
+}
+
+int rmo_decode_batch_at(const rmo_decoder *d, const float *llr, int64_t n_frames, int64_t frame0,
+                        uint8_t *out_bits, float *out_pm, int n_threads)
+{
+    if (!d || n_frames < 0 || frame0 < 0 || (1 << d->m) < 8)
         return -1;
     if (n_threads < 1)
         n_threads = 1;
@@ -852,7 +970,7 @@ int rmo_decode_batch(const rmo_decoder *d, const float *llr, int64_t n_frames, u
             break;
         if (f1 > n_frames)
             f1 = n_frames;
-        jobs[t] = (job_t){d, llr, f0, f1, out_bits, out_pm};
+        jobs[t] = (job_t){d, llr, f0, f1, frame0, out_bits, out_pm};
         pthread_create(&th[t], NULL, batch_worker, &jobs[t]);
         started++;
     }

@@ -18,6 +18,10 @@
 #define RMO_PERM_NONE 0   /* FHT-FSCL: identity, no permutation domain; the
                              list starts from one path (others inactive)   */
 #define RMO_PERM_PFHT 1   /* p-FHT-FSCL: Alg. 2 permutation domain      */
+#define RMO_PERM_FRESH 2  /* p-FHT-FSCL with maps drawn afresh for every frame:
+                             decoder d of frame f draws from the SplitMix64
+                             stream whose state is one step from
+                             seed ^ (f << 20 | d), in the fixed draw order   */
 
 typedef struct rmo_decoder rmo_decoder;
 
@@ -30,14 +34,20 @@ typedef struct rmo_decoder rmo_decoder;
 rmo_decoder *rmo_create(int m, int r, int P, int L, int perm_mode, uint64_t seed);
 void rmo_destroy(rmo_decoder *d);
 
-/* Decode one received LLR vector y (N floats).  xhat: N bytes (0/1). */
+/* Decode one received LLR vector y (N floats).  xhat: N bytes (0/1).
+ * rmo_decode_frame also names the frame's index (used by the fresh mode). */
 int rmo_decode(const rmo_decoder *d, const float *y, uint8_t *xhat, float *pm);
+int rmo_decode_frame(const rmo_decoder *d, const float *y, int64_t frame, uint8_t *xhat, float *pm);
 
 /* Decode n_frames frames; out_bits holds N/8 bytes per frame, bit i of the
  * codeword at byte i>>3, bit i&7.  Frames are sharded over n_threads threads,
  * each running the single-threaded decoder above unchanged. */
 int rmo_decode_batch(const rmo_decoder *d, const float *llr, int64_t n_frames,
                      uint8_t *out_bits, float *out_pm, int n_threads);
+/* As rmo_decode_batch, the frames numbered frame0, frame0+1, ... (the index
+ * that keys the maps of the fresh mode). */
+int rmo_decode_batch_at(const rmo_decoder *d, const float *llr, int64_t n_frames, int64_t frame0,
+                        uint8_t *out_bits, float *out_pm, int n_threads);
 
 /* Pieces exposed for the pin tests. */
 int rmo_info_set(int m, int r, uint8_t *is_info);                 /* N flags */
@@ -51,6 +61,7 @@ int rmo_fhtl(int s, int L, const float *alpha, const float *pm_in,
 int rmo_schedule(int m, int r, int perm_mode, int *out, int cap);  /* (kind,r,m) triples */
 int rmo_perm_count(const rmo_decoder *d);
 int rmo_perm_export(const rmo_decoder *d, uint16_t *rows, uint16_t *b, int *mdim, int cap);
+int rmo_perm_export_frame(const rmo_decoder *d, int64_t frame, uint16_t *rows, uint16_t *b, int *mdim, int cap);
 uint64_t rmo_splitmix64_next(uint64_t *state);
 
 #endif

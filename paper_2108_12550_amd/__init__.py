@@ -13,15 +13,16 @@ from math import comb
 
 from . import _lib
 from ._lib import (RM_E_AGAIN, RM_E_HIP, RM_E_INVAL, RM_E_NOMEM, RM_E_PTR, RM_E_UNSUPPORTED, RM_MIXED_MAX_SEGMENTS,
-                   RM_OK, RM_PERM_NONE, RM_PERM_PFHT, rm_completion, rm_config, rm_decode_batch, rm_decoder_create,
+                   RM_OK, RM_PERM_FRESH, RM_PERM_NONE, RM_PERM_PFHT, rm_completion, rm_config, rm_decode_batch, rm_decoder_create,
                    rm_decoder_create_ex, rm_decoder_destroy, rm_decoder_info, rm_decoder_set_stream, rm_last_error,
                    rm_mixed_autotune, rm_mixed_capture, rm_mixed_create, rm_mixed_decode, rm_mixed_destroy,
                    rm_mixed_replay, rm_mixed_set_grid, rm_mixed_set_stream, rm_mixed_supported, rm_mixed_tuning,
-                   rm_perm_tables, rm_request, rm_segment, rm_server_config, rm_server_create, rm_server_destroy,
+                   rm_perm_tables, rm_perm_tables_frame, rm_request, rm_segment, rm_server_config, rm_server_create, rm_server_destroy,
                    rm_server_now_us, rm_server_pending, rm_server_poll, rm_server_register_pool, rm_server_run_trace,
                    rm_server_submit, rm_server_supported, rm_supported)
 
 __all__ = ["Decoder", "MixedLauncher", "perm_tables", "code_dimension", "RM_PERM_NONE", "RM_PERM_PFHT",
+           "RM_PERM_FRESH", "rm_perm_tables_frame",
            "RM_MIXED_MAX_SEGMENTS", "rm_config", "rm_segment", "rm_decode_batch", "rm_decoder_create",
            "rm_decoder_create_ex", "rm_decoder_destroy", "rm_decoder_info", "rm_decoder_set_stream",
            "rm_last_error", "rm_perm_tables", "rm_supported", "rm_mixed_create", "rm_mixed_supported",
@@ -267,10 +268,11 @@ class Server:
         self.close()
 
 
-def perm_tables(m: int, r: int, P: int, L: int, seed: int, perm_mode: int = RM_PERM_PFHT):
-    """Every affine map the decoder draws, in draw order: list of (rows, b)."""
+def perm_tables(m: int, r: int, P: int, L: int, seed: int, perm_mode: int = RM_PERM_PFHT, frame: int = 0):
+    """Every affine map the decoder draws (for frame `frame` of a call in the
+    fresh mode), in draw order: list of (rows, b)."""
     cap = P * (L + 2 * L * m)
-    n, rows, b, md = rm_perm_tables(m, r, P, L, seed, perm_mode, cap)
+    n, rows, b, md = rm_perm_tables_frame(m, r, P, L, seed, perm_mode, frame, cap)
     if n < 0:
         raise RMError(n, rm_last_error())
     return [(list(rows[16 * k:16 * k + md[k]]), int(b[k])) for k in range(n)]

@@ -21,9 +21,11 @@ RM_E_AGAIN = -6
 
 RM_PERM_NONE = 0
 RM_PERM_PFHT = 1
+RM_PERM_FRESH = 2
 
 EXPORTED = ("rm_decoder_create", "rm_decoder_create_ex", "rm_decode_batch", "rm_decoder_destroy",
-            "rm_decoder_set_stream", "rm_decoder_info", "rm_perm_tables", "rm_supported", "rm_last_error",
+            "rm_decoder_set_stream", "rm_decoder_info", "rm_perm_tables", "rm_perm_tables_frame", "rm_supported",
+            "rm_last_error",
             "rm_mixed_create", "rm_mixed_supported", "rm_mixed_set_stream", "rm_mixed_set_grid", "rm_mixed_decode",
             "rm_mixed_capture", "rm_mixed_replay", "rm_mixed_autotune", "rm_mixed_destroy",
             "rm_server_create", "rm_server_supported", "rm_server_now_us", "rm_server_register_pool",
@@ -102,6 +104,10 @@ def load() -> ctypes.CDLL:
     L.rm_perm_tables.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
                                  ctypes.c_int, P(ctypes.c_uint16), P(ctypes.c_uint16), P(ctypes.c_int),
                                  ctypes.c_int]
+    L.rm_perm_tables_frame.restype = ctypes.c_int
+    L.rm_perm_tables_frame.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                       ctypes.c_int, ctypes.c_int64, P(ctypes.c_uint16), P(ctypes.c_uint16),
+                                       P(ctypes.c_int), ctypes.c_int]
     L.rm_supported.restype = ctypes.c_int
     L.rm_supported.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     L.rm_last_error.restype = ctypes.c_char_p
@@ -183,6 +189,14 @@ def rm_perm_tables(m: int, r: int, P: int, L: int, seed: int, perm_mode: int, ca
     b = (ctypes.c_uint16 * cap)()
     md = (ctypes.c_int * cap)()
     n = load().rm_perm_tables(m, r, P, L, ctypes.c_uint64(seed), perm_mode, rows, b, md, cap)
+    return n, rows, b, md
+
+
+def rm_perm_tables_frame(m: int, r: int, P: int, L: int, seed: int, perm_mode: int, frame: int, cap: int):
+    rows = (ctypes.c_uint16 * (16 * cap))()
+    b = (ctypes.c_uint16 * cap)()
+    md = (ctypes.c_int * cap)()
+    n = load().rm_perm_tables_frame(m, r, P, L, ctypes.c_uint64(seed), perm_mode, frame, rows, b, md, cap)
     return n, rows, b, md
 
 

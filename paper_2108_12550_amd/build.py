@@ -29,7 +29,7 @@ FLAGS = [
 ]
 SOURCES = ["rmdec_inst_f.hip", "rmdec_inst_e.hip", "rmdec_serve_l8.hip", "rmdec_serve_l4.hip", "rmdec_serve_l1.hip",
            "rmdec_mixed.hip", "rmdec_inst_a.hip", "rmdec_inst_b.hip", "rmdec_inst_c.hip", "rmdec_inst_d.hip",
-           "rmdec_host.hip", "rmdec_serve.hip"]
+           "rmdec_host.hip", "rmdec_serve.hip", "rmdec_fresh.hip"]
 
 
 def _compile(src: str) -> str:

@@ -39,8 +39,9 @@ struct KernelArgs {
     const float *llr;
     uint8_t *out_bits;
     float *out_pm;
-    const uint32_t *maps; // [P][maps_per_dec][kMapWords]
+    const uint32_t *maps; // [P][maps_per_dec][kMapWords] (per frame when frame_stride > 0)
     int64_t n_frames;
+    int64_t frame_stride; // words between frames' tables; 0: one table set for all frames
     int P;
     int maps_per_dec;
     int pfht; // 1: permutation domain on; 0: identity, no permutation domain
@@ -1263,7 +1264,9 @@ template <int M, int R, int L, int D>
 __device__ __forceinline__ void decode_batch_frame(const KernelArgs &args, int64_t f, unsigned char *slice, int lane)
 {
     constexpr int N = 1 << M;
-    decode_frame<M, R, L, D>(args, args.llr + f * N, args.out_bits + f * (N / 8), args.out_pm ? args.out_pm + f : nullptr,
+    KernelArgs fa = args;
+    fa.maps += f * args.frame_stride;
+    decode_frame<M, R, L, D>(fa, args.llr + f * N, args.out_bits + f * (N / 8), args.out_pm ? args.out_pm + f : nullptr,
                              slice, lane);
 }
 

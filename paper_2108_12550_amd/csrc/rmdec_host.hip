@@ -47,9 +47,10 @@ KernelArgs batch_args(const rm_decoder *d, const float *llr, int64_t n_frames, u
     a.out_pm = out_metric;
     a.maps = d->d_maps;
     a.n_frames = n_frames;
+    a.frame_stride = 0;
     a.P = d->cfg.P;
     a.maps_per_dec = d->maps_per_dec;
-    a.pfht = d->cfg.perm_mode == RM_PERM_PFHT;
+    a.pfht = d->cfg.perm_mode != RM_PERM_NONE;
     a.waves = d->cfg.waves_per_block;
     return a;
 }
@@ -123,6 +124,33 @@ Affine draw_affine(int m, SplitMix64 &rng)
     return a;
 }
 
+// The fresh mode's draw: row k of A redrawn until it lies outside the span of
+// rows 0..k-1 (tested by reduction against an XOR basis kept by leading
+// bit), then b.
+Affine draw_affine_rowwise(int m, SplitMix64 &rng)
+{
+    Affine a;
+    a.m = m;
+    const uint32_t mask = (1u << m) - 1u;
+    uint32_t basis[16] = {}; // basis[h]: a vector of the span whose leading bit is h
+    for (int k = 0; k < m; k++) {
+        for (;;) {
+            const uint32_t r = (uint32_t)(rng.next() & mask);
+            uint32_t x = r;
+            for (int h = m - 1; h >= 0; h--)
+                if (((x >> h) & 1u) && basis[h])
+                    x ^= basis[h];
+            if (x) {
+                basis[31 - __builtin_clz(x)] = x;
+                a.row[k] = r;
+                break;
+            }
+        }
+    }
+    a.b = (uint32_t)(rng.next() & mask);
+    return a;
+}
+
 Affine identity(int m)
 {
     Affine a;
@@ -153,6 +181,27 @@ Draw draw_all(int m, int r, int P, int L, uint64_t seed, int pfht)
         for (int v = 0; v < d.nperm; v++)
             for (int c = 0; c < 2 * L; c++)
                 d.cand[((size_t)p * d.nperm + v) * 2 * L + c] = draw_affine(m - v, rng);
+    }
+    return d;
+}
+
+// The fresh mode's draw for one frame: decoder p draws, in the order of the
+// fixed tables but row by row, from the SplitMix64 stream whose state is one
+// step from seed ^ (frame << 20 | p).
+Draw draw_fresh(int m, int r, int P, int L, uint64_t seed, int64_t frame)
+{
+    Draw d;
+    d.nperm = spine_perm_nodes(m, r);
+    d.init.resize((size_t)P * L);
+    d.cand.resize((size_t)P * d.nperm * 2 * L);
+    for (int p = 0; p < P; p++) {
+        SplitMix64 key{seed ^ (((uint64_t)frame << 20) | (uint64_t)p)};
+        SplitMix64 rng{key.next()};
+        for (int l = 0; l < L; l++)
+            d.init[(size_t)p * L + l] = draw_affine_rowwise(m, rng);
+        for (int v = 0; v < d.nperm; v++)
+            for (int c = 0; c < 2 * L; c++)
+                d.cand[((size_t)p * d.nperm + v) * 2 * L + c] = draw_affine_rowwise(m - v, rng);
     }
     return d;
 }
@@ -209,7 +258,7 @@ int check_params(int m, int r, int P, int L, int perm_mode)
         return fail(RM_E_INVAL, "P must be in [1, 1024]");
     if (!(L == 1 || L == 2 || L == 4 || L == 8))
         return fail(RM_E_INVAL, "L must be 1, 2, 4 or 8");
-    if (perm_mode != RM_PERM_NONE && perm_mode != RM_PERM_PFHT)
+    if (perm_mode != RM_PERM_NONE && perm_mode != RM_PERM_PFHT && perm_mode != RM_PERM_FRESH)
         return fail(RM_E_INVAL, "unknown perm_mode");
     return RM_OK;
 }
@@ -241,12 +290,21 @@ int rm_supported(int m, int r, int L, int perm_mode)
 int rm_perm_tables(int m, int r, int P, int L, uint64_t seed, int perm_mode, uint16_t *rows, uint16_t *b, int *mdim,
                    int cap)
 {
+    return rm_perm_tables_frame(m, r, P, L, seed, perm_mode, 0, rows, b, mdim, cap);
+}
+
+int rm_perm_tables_frame(int m, int r, int P, int L, uint64_t seed, int perm_mode, int64_t frame, uint16_t *rows,
+                         uint16_t *b, int *mdim, int cap)
+{
     int rc = check_params(m, r, P, L, perm_mode);
     if (rc != RM_OK)
         return rc;
     if (!rows || !b || !mdim)
         return fail(RM_E_INVAL, "null output array");
-    const Draw d = draw_all(m, r, P, L, seed, perm_mode == RM_PERM_PFHT);
+    if (frame < 0 || frame >= ((int64_t)1 << 43))
+        return fail(RM_E_INVAL, "frame outside [0, 2^43)");
+    const Draw d = perm_mode == RM_PERM_FRESH ? draw_fresh(m, r, P, L, seed, frame)
+                                              : draw_all(m, r, P, L, seed, perm_mode == RM_PERM_PFHT);
     const int total = P * (L + d.nperm * 2 * L);
     if (cap < total)
         return fail(RM_E_INVAL, "cap too small: need " + std::to_string(total));
@@ -287,14 +345,15 @@ rm_decoder *rm_decoder_create_ex(const rm_config *cfg)
     }
     const int m = cfg->m, r = cfg->r, P = cfg->P, L = cfg->L;
     const int pfht = cfg->perm_mode == RM_PERM_PFHT;
-    const Draw d = draw_all(m, r, P, L, cfg->seed, pfht);
+    const int fresh = cfg->perm_mode == RM_PERM_FRESH;
+    const Draw d = fresh ? Draw{{}, {}, spine_perm_nodes(m, r)} : draw_all(m, r, P, L, cfg->seed, pfht);
     const int mpd = 2 * L + 4 * L * d.nperm;
 
     // Per decoder: [0,L) initial maps, [L,2L) their inverses; for spine node v:
     // [2L+4Lv, 2L+4Lv+2L) candidate maps (at v = 0 composed after the initial
     // map of path c mod L), then their inverses.
-    std::vector<uint32_t> host((size_t)P * mpd * kMapWords);
-    for (int p = 0; p < P; p++) {
+    std::vector<uint32_t> host(fresh ? 0 : (size_t)P * mpd * kMapWords);
+    for (int p = 0; p < (fresh ? 0 : P); p++) {
         uint32_t *base = host.data() + (size_t)p * mpd * kMapWords;
         std::vector<std::vector<uint32_t>> init_q(L);
         for (int l = 0; l < L; l++) {
@@ -330,6 +389,16 @@ rm_decoder *rm_decoder_create_ex(const rm_config *cfg)
     dec->kern = k;
     dec->stream = nullptr;
     dec->table_bytes = host.size() * sizeof(uint32_t);
+    dec->fresh_chunk = 0;
+    if (fresh) {
+        // the tables of up to 16384 frames at a time (enough waves to fill the
+        // chip), at most 512 MiB
+        const int64_t per_frame = (int64_t)P * mpd * kMapWords * sizeof(uint32_t);
+        int64_t chunk = ((int64_t)512 << 20) / per_frame;
+        chunk = chunk < 1 ? 1 : (chunk > 16384 ? 16384 : chunk);
+        dec->fresh_chunk = chunk;
+        dec->table_bytes = (size_t)(chunk * per_frame);
+    }
     int wpb = cfg->waves_per_block;
     if (wpb == 0) {
         wpb = 65536 / k->lds_bytes_per_wave;
@@ -344,7 +413,7 @@ rm_decoder *rm_decoder_create_ex(const rm_config *cfg)
     hipError_t e = hipGetDevice(&dec->device);
     if (e == hipSuccess)
         e = hipMalloc((void **)&dec->d_maps, dec->table_bytes);
-    if (e == hipSuccess)
+    if (e == hipSuccess && !fresh)
         e = hipMemcpy(dec->d_maps, host.data(), dec->table_bytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         fail(RM_E_HIP, std::string("HIP error at create: ") + hipGetErrorString(e));
@@ -416,6 +485,8 @@ int rm_decode_batch(rm_decoder *d, const float *llr, int64_t n_frames, uint8_t *
         rc = check_device_ptr(out_metric, "out_metric");
     if (rc != RM_OK)
         return rc;
+    if (d->cfg.perm_mode == RM_PERM_FRESH)
+        return fresh_decode(d, llr, n_frames, out_bits, out_metric);
     KernelArgs a = batch_args(d, llr, n_frames, out_bits, out_metric);
     const int64_t blocks64 = (n_frames + a.waves - 1) / a.waves;
     const int blocks = (int)(blocks64 > (1 << 30) ? (1 << 30) : blocks64);

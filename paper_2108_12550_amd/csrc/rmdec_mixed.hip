@@ -126,6 +126,8 @@ int prepare(rm_mixed *mx, const rm_segment *segs, int n_segs, MixedArgs &a, std:
             return fail(RM_E_INVAL, "n_frames < 0");
         if (g.n_frames > 0xFFFFFFFFll)
             return fail(RM_E_INVAL, "segment too long for one launch");
+        if (g.dec->cfg.perm_mode == RM_PERM_FRESH)
+            return fail(RM_E_UNSUPPORTED, "fresh-permutation decoders run through rm_decode_batch only");
         const int slot = fused_slot(g.dec->cfg.m, g.dec->cfg.r, g.dec->cfg.L);
         if (slot < 0)
             return fail(RM_E_UNSUPPORTED, "code not compiled into the fused kernel");

@@ -373,6 +373,8 @@ int rm_server_submit(rm_server *s, const rm_request *req, uint64_t *ticket)
     const rm_decoder *d = req->dec;
     if (!rm_server_supported(d->cfg.m, d->cfg.r, d->cfg.L))
         return fail(RM_E_UNSUPPORTED, "no serving kernel for this code and list size");
+    if (d->cfg.perm_mode == RM_PERM_FRESH)
+        return fail(RM_E_UNSUPPORTED, "fresh-permutation decoders run through rm_decode_batch only");
     const int N = d->N;
     const int64_t need = req->llr_on_device ? 0 : 4 * (int64_t)N;
     if (req->llr_on_device) {

@@ -44,6 +44,32 @@ def test_perm_draw_matches_oracle(m, r, P, L, seed):
         assert b == rb
 
 
+@pytest.mark.parametrize("m,r,P,L,seed", [(9, 2, 4, 4, 0), (8, 3, 2, 8, 3), (7, 2, 3, 1, 9), (10, 2, 2, 1, 7),
+                                          (5, 1, 2, 4, 5)])
+def test_fresh_draw_matches_oracle_per_frame(m, r, P, L, seed):
+    dec = oracle.OracleDecoder(m, r, P, L, seed=seed, perm_mode=oracle.PERM_FRESH)
+    seen = set()
+    for frame in (0, 1, 2, 777, (1 << 43) - 1):
+        mine = rmd.perm_tables(m, r, P, L, seed, rmd.RM_PERM_FRESH, frame=frame)
+        ref = dec.perms(frame)
+        assert len(mine) == len(ref)
+        for (rows, b), (rrows, rb) in zip(mine, ref):
+            assert list(rows) == [int(x) for x in rrows]
+            assert b == rb
+        seen.add(tuple((tuple(rw), b) for rw, b in mine))
+    assert len(seen) == 5  # every frame draws its own maps
+
+
+def test_fresh_draw_frame_range_checked():
+    for frame in (-1, 1 << 43):
+        n, *_ = _lib.rm_perm_tables_frame(7, 2, 1, 1, 0, rmd.RM_PERM_FRESH, frame, 64)
+        assert n == _lib.RM_E_INVAL
+
+
+def test_fixed_modes_ignore_frame():
+    assert rmd.perm_tables(8, 2, 3, 2, 5, frame=9) == rmd.perm_tables(8, 2, 3, 2, 5, frame=0)
+
+
 def test_perm_draw_none_mode_is_identity():
     maps = rmd.perm_tables(7, 2, 1, 1, 0, rmd.RM_PERM_NONE)
     assert maps == [([1 << k for k in range(7)], 0)]

@@ -378,6 +378,10 @@ def test_plain_list_fer_matches_fig5(name, L, ebn0, n):
     ("p-FHT-FSC-1", oracle.PERM_PFHT, 1, "3.0", 12000),
     ("p-FHT-FSC-2", oracle.PERM_PFHT, 2, "3.0", 12000),
     ("p-FHT-FSCL-4", oracle.PERM_PFHT, 4, "2.5", 3000),
+    # maps drawn afresh for every frame: the same curves
+    ("p-FHT-FSC-1", oracle.PERM_FRESH, 1, "3.0", 12000),
+    ("p-FHT-FSC-2", oracle.PERM_FRESH, 2, "2.5", 8000),
+    ("p-FHT-FSCL-4", oracle.PERM_FRESH, 4, "2.5", 3000),
 ])
 def test_fer_matches_fig5(name, mode, L, ebn0, n):
     pub = GOLDEN["fer_rm29"][name][ebn0]
