@@ -1144,8 +1144,8 @@ __device__ __forceinline__ Ctx<M, R, L, D> frame_ctx(const KernelArgs &args, uns
 }
 
 template <int M, int R, int L, int D>
-__device__ __forceinline__ FrameBest decode_decoders(const KernelArgs &args, const float *src, unsigned char *slice,
-                                                     int lane, int d_begin, int d_end)
+__device__ __forceinline__ FrameBest decode_decoders(const KernelArgs &args, const uint32_t *maps, const float *src,
+                                                     unsigned char *slice, int lane, int d_begin, int d_end)
 {
     using Sh = Shape<M, R, L, D>;
     constexpr int N = Sh::N;
@@ -1166,13 +1166,17 @@ __device__ __forceinline__ FrameBest decode_decoders(const KernelArgs &args, con
         for (int t = 0; t < D; t++) {
             const int dd = d0 + t < d_end ? d0 + t : d_end - 1;
             // stored with columns and offset as byte offsets of float elements
-            const uint4 *mg = (const uint4 *)(args.maps + (size_t)dd * args.maps_per_dec * kMapWords);
+            const uint4 *mg = (const uint4 *)(maps + (size_t)dd * args.maps_per_dec * kMapWords);
             uint4 *ml = (uint4 *)(c.maps_all() + t * Sh::MAPS_PER_DEC * kMapWords);
             for (int i = c.lane; i < args.maps_per_dec * (kMapWords / 4); i += kWave)
                 ml[i] = mg[i];
         }
         wave_sync();
-        const RootRes<M, R, L, D> r = decode_root<M, R, L, D>(c);
+        // lane-derived constants recomputed per pass (an opaque copy of the
+        // lane id), rather than hoisted to the frame and spilled
+        int dlane;
+        asm volatile("v_mov_b32 %0, %1" : "=v"(dlane) : "v"(lane));
+        const RootRes<M, R, L, D> r = decode_root<M, R, L, D>(frame_ctx<M, R, L, D>(args, slice, dlane));
         // Alg. 5 in decoder order: first minimum over the list, replace only if strictly smaller
 #pragma unroll
         for (int t = 0; t < D; t++) {
@@ -1203,8 +1207,8 @@ __device__ __forceinline__ FrameBest decode_decoders(const KernelArgs &args, con
 }
 
 template <int M, int R, int L, int D>
-__device__ __forceinline__ void emit_codeword(const KernelArgs &args, FrameBest fb, uint8_t *ob, float *opm,
-                                              unsigned char *slice, int lane)
+__device__ __forceinline__ void emit_codeword(const KernelArgs &args, const uint32_t *maps, FrameBest fb, uint8_t *ob,
+                                              float *opm, unsigned char *slice, int lane)
 {
     using Sh = Shape<M, R, L, D>;
     constexpr int N = Sh::N;
@@ -1212,7 +1216,7 @@ __device__ __forceinline__ void emit_codeword(const KernelArgs &args, FrameBest 
     const Ctx<M, R, L, D> c = frame_ctx<M, R, L, D>(args, slice, lane);
     const uint64_t *xb = c.xbest();
     // the winner back in channel order, packed
-    const uint32_t *mi = args.maps + (size_t)fb.bestmap * kMapWords;
+    const uint32_t *mi = maps + (size_t)fb.bestmap * kMapWords;
     uint32_t col[M + 1];
 #pragma unroll
     for (int k = 0; k < M; k++)
@@ -1252,11 +1256,11 @@ __device__ __forceinline__ void emit_codeword(const KernelArgs &args, FrameBest 
 }
 
 template <int M, int R, int L, int D>
-__device__ __forceinline__ void decode_frame(const KernelArgs &args, const float *src, uint8_t *ob, float *opm,
-                                             unsigned char *slice, int lane)
+__device__ __forceinline__ void decode_frame(const KernelArgs &args, const uint32_t *maps, const float *src, uint8_t *ob,
+                                             float *opm, unsigned char *slice, int lane)
 {
-    const FrameBest fb = decode_decoders<M, R, L, D>(args, src, slice, lane, 0, args.P);
-    emit_codeword<M, R, L, D>(args, fb, ob, opm, slice, lane);
+    const FrameBest fb = decode_decoders<M, R, L, D>(args, maps, src, slice, lane, 0, args.P);
+    emit_codeword<M, R, L, D>(args, maps, fb, ob, opm, slice, lane);
 }
 
 // frame f of a contiguous batch
@@ -1264,10 +1268,8 @@ template <int M, int R, int L, int D>
 __device__ __forceinline__ void decode_batch_frame(const KernelArgs &args, int64_t f, unsigned char *slice, int lane)
 {
     constexpr int N = 1 << M;
-    KernelArgs fa = args;
-    fa.maps += f * args.frame_stride;
-    decode_frame<M, R, L, D>(fa, args.llr + f * N, args.out_bits + f * (N / 8), args.out_pm ? args.out_pm + f : nullptr,
-                             slice, lane);
+    decode_frame<M, R, L, D>(args, args.maps + f * args.frame_stride, args.llr + f * N, args.out_bits + f * (N / 8),
+                             args.out_pm ? args.out_pm + f : nullptr, slice, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -1399,7 +1401,7 @@ __device__ __forceinline__ void serve_tile(const ServeArgs &a, const KernelArgs 
 {
     for (uint32_t k = 0; k < t.count; k++) {
         const Job j = a.jobs[t.first + k];
-        decode_frame<C::M, C::R, C::L, C::D>(ka, j.llr, a.out_bits + (size_t)j.out * kServeBitsStride, a.out_pm + j.out,
+        decode_frame<C::M, C::R, C::L, C::D>(ka, ka.maps, j.llr, a.out_bits + (size_t)j.out * kServeBitsStride, a.out_pm + j.out,
                                              slice, lane);
     }
 }
@@ -1459,7 +1461,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
             const Job j = a.jobs[tile.first + k];
             FrameBest fb = {__builtin_inff(), 0};
             int idx = 0;
-            ((code == idx++ ? (fb = decode_decoders<Codes::M, Codes::R, Codes::L, Codes::D>(ka, j.llr, slice, lane,
+            ((code == idx++ ? (fb = decode_decoders<Codes::M, Codes::R, Codes::L, Codes::D>(ka, ka.maps, j.llr, slice, lane,
                                                                                            d_begin, d_end),
                                0)
                             : 0),
@@ -1476,8 +1478,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
                 const FrameBest wb = {s_best[win], s_map[win]};
                 idx = 0;
                 ((code == idx++ ? (emit_codeword<Codes::M, Codes::R, Codes::L, Codes::D>(
-                                       ka, wb, a.out_bits + (size_t)j.out * kServeBitsStride, a.out_pm + j.out, slice,
-                                       lane),
+                                       ka, ka.maps, wb, a.out_bits + (size_t)j.out * kServeBitsStride,
+                                       a.out_pm + j.out, slice, lane),
                                    0)
                                 : 0),
                  ...);
