@@ -57,7 +57,7 @@ typedef struct rm_config {
     int m;               /* 3 <= m <= 10, N = 2^m                                  */
     int r;               /* 1 <= r <= m-1                                          */
     int P;               /* parallel decoders per frame (paper's M), 1..1024      */
-    int L;               /* list size per decoder: 1, 2, 4 or 8                   */
+    int L;               /* list size per decoder: 1, 2, 4, 8, 16, 32 or 64       */
     uint64_t seed;       /* seed of the permutation draw (SplitMix64)             */
     int perm_mode;       /* RM_PERM_PFHT, RM_PERM_NONE or RM_PERM_FRESH           */
     int waves_per_block; /* 0 = library choice; else 1..4 wavefronts per block   */

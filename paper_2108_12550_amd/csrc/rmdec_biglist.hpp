@@ -1,0 +1,635 @@
+// rmdec_biglist.hpp -- p-FHT-FSCL / FHT-FSCL with large lists (L = 16, 32,
+// 64): one workgroup of 512 threads per frame, the L paths' LLR and codeword
+// stacks in LDS.
+//
+// The register-resident kernels hold a path in 64/L lanes, which cannot hold
+// a half-length node vector once L exceeds 8.  Here the paths live in LDS:
+// the LLRs of level s (1 <= s < m) take L*2^s floats (L*N floats in all),
+// the codeword bits of both children of the node at level s take 2*L*2^s
+// bits.  Thread t of a path-parallel step serves path t / G (G = 512 / L
+// threads per path); element-parallel steps stride over the path's row.
+//
+// The operations and their order are those of the batched kernels: Alg. 2
+// (candidate maps of the permutation domain, kept by the largest sum of
+// |f|, ties to the lower candidate), Alg. 3 and 4 (FHT list decoding with
+// the metric of Eq. (10); the min(L, 2^s) largest |F| per path, ties to the
+// lower index; candidates merged in the order (metric, path, rank)), the SPC
+// list rules of Eqs. (2)-(6), and Alg. 5 over the P decoders.  Sums of
+// |alpha| and |f| follow the halving tree v[i] += v[i + w], w = n/2 .. 1.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rmdec_device.hpp"
+
+namespace rmdec {
+namespace big {
+
+constexpr int kThreads = 512;
+
+__host__ __device__ constexpr int words_of(int s) { return s >= 5 ? (1 << (s - 5)) : 1; }
+__host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
+
+// LDS layout in 32-bit words.
+template <int M, int L>
+struct Lay {
+    static constexpr int N = 1 << M;
+    static constexpr int G = kThreads / L; // threads per path
+    static constexpr int Y = 0;             // N floats: the channel LLRs
+    static constexpr int A = N;             // level s at A + L*(2^s - 2): L rows of 2^s floats
+    static constexpr int A_END = A + L * (N - 2);
+    // codeword bits: level s (3..M), side 0 (left child) and 1 (right)
+    static constexpr int xb_below(int s)
+    {
+        int w = 0;
+        for (int t = 3; t < s; t++)
+            w += 2 * L * words_of(t);
+        return w;
+    }
+    static constexpr int XB = A_END;
+    static constexpr int XB_END = XB + xb_below(M + 1);
+    // per level s: metrics and ancestors of both children's outputs
+    static constexpr int PM = XB_END;            // [M+1][2][L] floats
+    static constexpr int ANC = PM + (M + 1) * 2 * L; // [M+1][2][L] ints
+    // per permutation-domain node (by level): kept candidates, their source path and metric
+    static constexpr int SEL = ANC + (M + 1) * 2 * L; // [M+1][2L]
+    static constexpr int ORIG = SEL + (M + 1) * 2 * L; // [M+1][L]
+    static constexpr int PPM = ORIG + (M + 1) * L;     // [M+1][L]
+    static constexpr int SCR = PPM + (M + 1) * L;      // 2L floats: LM values, SPC candidate metrics
+    static constexpr int PM0 = SCR + 2 * L;            // L: the root's input metrics
+    static constexpr int SIDX = PM0 + L;               // L: FHT survivors' index and sign
+    static constexpr int PAR = SIDX + L;               // L: SPC parities of the input paths
+    // SPC list state, two copies: source path, parity, metric, flips (2 words,
+    // at an even word offset for 8-byte accesses)
+    static constexpr int SPC = (PAR + L + 1) & ~1;
+    static constexpr int SPC_ONE = 5 * L;
+    static constexpr int BEST = SPC + 2 * SPC_ONE; // the frame's best codeword, N bits
+    static constexpr int MISC = BEST + (N / 32 > 0 ? N / 32 : 1);
+    static constexpr int WORDS = MISC + 4; // best metric, improved flag, winner
+    static constexpr int BYTES = WORDS * 4;
+
+    static constexpr int a_off(int s) { return A + L * ((1 << s) - 2); }
+    static constexpr int xb_off(int s, int side) { return XB + xb_below(s) + side * L * words_of(s); }
+};
+
+template <int S>
+struct MapR {
+    uint32_t col[S];
+    uint32_t b;
+};
+
+// a stored map (columns and offset as byte offsets, times 4) into registers
+template <int S>
+__device__ __forceinline__ void load_map(const uint32_t *mp, MapR<S> &m)
+{
+#pragma unroll
+    for (int k = 0; k < S; k++)
+        m.col[k] = mp[k] >> 2;
+    m.b = mp[kMapB] >> 2;
+}
+
+template <int S>
+__device__ __forceinline__ uint32_t apply_map(const MapR<S> &m, uint32_t i)
+{
+    uint32_t p = m.b;
+#pragma unroll
+    for (int k = 0; k < S; k++)
+        p ^= ((i >> k) & 1u) ? m.col[k] : 0u;
+    return p;
+}
+
+__device__ __forceinline__ float big_fminsum(float a, float b)
+{
+    const float m = fminf(fabsf(a), fabsf(b));
+    return ((__float_as_uint(a) ^ __float_as_uint(b)) & 0x80000000u) ? -m : m;
+}
+__device__ __forceinline__ float big_g(float a, float b, uint32_t c) { return b + (1.0f - 2.0f * (float)c) * a; }
+
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int o)
+{
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, o);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), o);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <int M, int L>
+struct BigCtx {
+    using Ly = Lay<M, L>;
+    uint32_t *w;            // LDS words
+    const uint32_t *dmaps;  // this decoder's maps
+    int tid;
+    int pfht;
+
+    __device__ float *f(int off) const { return (float *)(w + off); }
+    __device__ int *i(int off) const { return (int *)(w + off); }
+    __device__ float *y() const { return f(Ly::Y); }
+    __device__ float *a(int s) const { return f(Ly::a_off(s)); } // row l at a(s) + l*2^s
+    __device__ uint32_t *xb(int s, int side) const { return w + Ly::xb_off(s, side); }
+    __device__ float *pm(int s, int side) const { return f(Ly::PM + (s * 2 + side) * L); }
+    __device__ int *anc(int s, int side) const { return i(Ly::ANC + (s * 2 + side) * L); }
+    __device__ int *sel(int s) const { return i(Ly::SEL + s * 2 * L); }
+    __device__ int *orig(int s) const { return i(Ly::ORIG + s * L); }
+    __device__ float *ppm(int s) const { return f(Ly::PPM + s * L); }
+    __device__ const uint32_t *map(int k) const { return dmaps + (size_t)k * kMapWords; }
+};
+
+// bit j of path row l at level s (row of words_of(s) words)
+template <int S>
+__device__ __forceinline__ uint32_t get_bit(const uint32_t *rows, int l, uint32_t j)
+{
+    return (rows[l * words_of(S) + (j >> 5)] >> (j & 31)) & 1u;
+}
+
+// The LLR of element i of the (unpermuted) input row of path l at level S:
+// the channel LLRs at the root, else the stored row.
+template <int M, int L, int S>
+__device__ __forceinline__ float in_llr(const BigCtx<M, L> &c, int l, uint32_t i)
+{
+    if constexpr (S == M)
+        return c.y()[i];
+    else
+        return c.a(S)[l * (1 << S) + i];
+}
+
+// ---------------------------------------------------------------------------
+// FHTL leaf RM(1,S) (Alg. 3, 4)
+// ---------------------------------------------------------------------------
+template <int M, int L, int S, int SIDE>
+__device__ void fhtl_leaf(const BigCtx<M, L> &c, const float *pm_in)
+{
+    using Ly = Lay<M, L>;
+    constexpr int n = 1 << S, h = n / 2, K = cmin(L, n), G = Ly::G;
+    constexpr int E = (n + G - 1) / G; // elements per thread of the path's group
+    static_assert(S < M, "leaf roots are not handled here");
+    const int l = c.tid / G, lt = c.tid % G;
+    float *F = c.a(S) + l * n;
+    float *scr = c.a(S - 1); // [L][h]: the sum of |alpha|
+    // Sum of |alpha| per path, halving tree
+    for (int i = lt; i < h; i += G)
+        scr[l * h + i] = fabsf(F[i]) + fabsf(F[i + h]);
+    __syncthreads();
+    for (int wdt = h / 2; wdt >= 1; wdt /= 2) {
+        for (int i = lt; i < wdt; i += G)
+            scr[l * h + i] = scr[l * h + i] + scr[l * h + i + wdt];
+        __syncthreads();
+    }
+    // FHT, strides 2^{S-1} .. 1
+    for (int t = 0; t < S; t++) {
+        const int hh = 1 << (S - t - 1);
+        for (int p = lt; p < h; p += G) {
+            const int i = (p / hh) * 2 * hh + (p % hh);
+            const float x = F[i], z = F[i + hh];
+            F[i] = z - x;
+            F[i + hh] = z + x;
+        }
+        __syncthreads();
+    }
+    // the path's elements in registers as keys: |F| bits, then the index
+    // complemented (ties to the lower index), then the sign
+    uint64_t key[E];
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+        const int i = lt + e * G;
+        if (i < n) {
+            const float v = F[i];
+            key[e] = ((uint64_t)(__float_as_uint(v) & 0x7FFFFFFFu) << 32) | ((uint64_t)(0xFFFFu - i) << 1) |
+                     (v < 0.0f ? 1u : 0u);
+        } else {
+            key[e] = 0;
+        }
+    }
+    const float llr_abs = scr[l * h];
+    const float pml = pm_in[l];
+    __syncthreads();
+    // K passes: the group's largest remaining key
+    float *metric = F;                                   // [K] per path, in the path's own row
+    uint16_t *cidx = (uint16_t *)(c.a(S - 1) + l * h); // [K] index << 1 | sign
+    for (int j = 0; j < K; j++) {
+        uint64_t b = 0;
+        int be = -1;
+#pragma unroll
+        for (int e = 0; e < E; e++)
+            if (key[e] > b) {
+                b = key[e];
+                be = e;
+            }
+        uint64_t gb = b;
+        for (int o = 1; o < G; o <<= 1) {
+            const uint64_t t = shfl_xor64(gb, o);
+            gb = t > gb ? t : gb;
+        }
+        if (be >= 0 && gb == b) {
+#pragma unroll
+            for (int e = 0; e < E; e++)
+                if (e == be)
+                    key[e] = 0;
+        }
+        if (lt == 0) {
+            const float absf = __uint_as_float((uint32_t)(gb >> 32));
+            const uint32_t idx = 0xFFFFu - (uint32_t)((gb >> 1) & 0xFFFFu);
+            metric[j] = pml + 0.5f * (llr_abs - absf);
+            cidx[j] = (uint16_t)((idx << 1) | (uint32_t)(gb & 1u));
+        }
+    }
+    __syncthreads();
+    // merge: rank of candidate (l, j) in the order (metric, l, j)
+    for (int q = c.tid; q < L * K; q += kThreads) {
+        const int ql = q / K, qj = q % K;
+        const float v = c.a(S)[ql * n + qj];
+        int rank = qj;
+        for (int o = 0; o < L; o++) {
+            if (o == ql)
+                continue;
+            const float *row = c.a(S) + o * n;
+            int lo = 0, hi = K; // entries before (v, ql): < v, or == v from a lower path
+            if (o < ql) {
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (row[mid] <= v)
+                        lo = mid + 1;
+                    else
+                        hi = mid;
+                }
+            } else {
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (row[mid] < v)
+                        lo = mid + 1;
+                    else
+                        hi = mid;
+                }
+            }
+            rank += lo;
+            if (rank >= L)
+                break;
+        }
+        if (rank < L) {
+            c.pm(S, SIDE)[rank] = v;
+            c.anc(S, SIDE)[rank] = ql;
+            c.i(Ly::SIDX)[rank] = (int)((const uint16_t *)(c.a(S - 1) + ql * h))[qj];
+        }
+    }
+    __syncthreads();
+    // the survivors' codewords: bit j = sign ^ parity(~(i | j))
+    uint32_t *xo = c.xb(S, SIDE);
+    for (int q = c.tid; q < L * words_of(S); q += kThreads) {
+        const int ql = q / words_of(S), wd = q % words_of(S);
+        const uint32_t code = (uint32_t)c.i(Ly::SIDX)[ql];
+        const uint32_t idx = code >> 1, sg = code & 1u;
+        uint32_t word = 0;
+        for (int bt = 0; bt < cmin(32, n); bt++) {
+            const uint32_t j = (uint32_t)(wd * 32 + bt);
+            word |= (sg ^ ((uint32_t)__popc(~(idx | j) & (uint32_t)(n - 1)) & 1u)) << bt;
+        }
+        xo[q] = word;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// SPCL leaf RM(S-1,S) (Eqs. (2)-(6))
+// ---------------------------------------------------------------------------
+template <int M, int L, int S, int SIDE>
+__device__ void spcl_leaf(const BigCtx<M, L> &c, const float *pm_in)
+{
+    using Ly = Lay<M, L>;
+    constexpr int n = 1 << S, G = Ly::G, W = words_of(S);
+    constexpr int TAU = cmin(L, n - 1);
+    constexpr int E = (n + G - 1) / G;
+    static_assert(S < M && S >= 3, "SPC leaf inside the tree");
+    const int l = c.tid / G, lt = c.tid % G;
+    const float *al = c.a(S) + l * n;
+    uint32_t *hd = (uint32_t *)c.a(S - 2); // [L][W] hard decisions
+    // hard decisions, Eq. (2)
+    for (int q = c.tid; q < L * W; q += kThreads) {
+        const int ql = q / W, wd = q % W;
+        const float *row = c.a(S) + ql * n;
+        uint32_t word = 0;
+        for (int bt = 0; bt < cmin(32, n); bt++)
+            word |= (row[wd * 32 + bt] < 0.0f ? 1u : 0u) << bt;
+        hd[q] = word;
+    }
+    // least reliable positions: keys |alpha| bits, then the index (ties to the lower index)
+    uint64_t key[E];
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+        const int i = lt + e * G;
+        key[e] = i < n ? (((uint64_t)(__float_as_uint(al[i]) & 0x7FFFFFFFu) << 32) | (uint32_t)i) : ~0ull;
+    }
+    __syncthreads();
+    if (c.tid < L) {
+        uint32_t p = 0;
+        for (int wd = 0; wd < W; wd++)
+            p ^= (uint32_t)__popc(hd[c.tid * W + wd]);
+        c.i(Ly::PAR)[c.tid] = (int)(p & 1u);
+    }
+    float *ao = c.a(S) + l * n;                          // [TAU+1] |alpha| at o_t
+    uint16_t *ord = (uint16_t *)(c.a(S - 1) + l * (n / 2)); // [TAU+1] o_t
+    for (int t = 0; t <= TAU; t++) {
+        uint64_t b = ~0ull;
+        int be = -1;
+#pragma unroll
+        for (int e = 0; e < E; e++)
+            if (key[e] < b) {
+                b = key[e];
+                be = e;
+            }
+        uint64_t gb = b;
+        for (int o = 1; o < G; o <<= 1) {
+            const uint64_t x = shfl_xor64(gb, o);
+            gb = x < gb ? x : gb;
+        }
+        if (be >= 0 && gb == b) {
+#pragma unroll
+            for (int e = 0; e < E; e++)
+                if (e == be)
+                    key[e] = ~0ull;
+        }
+        if (lt == 0) {
+            ao[t] = __uint_as_float((uint32_t)(gb >> 32));
+            ord[t] = (uint16_t)(gb & 0xFFFFu);
+        }
+    }
+    __syncthreads();
+    // list state: source path, parity, metric, flips (Eq. (3) for the start)
+    auto SP = [&](int b) { return c.i(Ly::SPC + b * Ly::SPC_ONE); };
+    auto CP = [&](int b) { return c.i(Ly::SPC + b * Ly::SPC_ONE + L); };
+    auto CPM = [&](int b) { return c.f(Ly::SPC + b * Ly::SPC_ONE + 2 * L); };
+    auto FL = [&](int b) { return (uint64_t *)c.i(Ly::SPC + b * Ly::SPC_ONE + 3 * L); };
+    if (c.tid < L) {
+        const int q = c.tid;
+        const int p = c.i(Ly::PAR)[q];
+        SP(0)[q] = q;
+        CP(0)[q] = p;
+        const float a0 = c.a(S)[q * n];
+        CPM(0)[q] = p ? pm_in[q] + a0 : pm_in[q];
+        FL(0)[q] = 0;
+    }
+    __syncthreads();
+    float *cpm2 = c.f(Ly::SCR); // [2L] candidate metrics
+    int cur = 0;
+    for (int t = 1; t <= TAU; t++) {
+        if (c.tid < 2 * L) {
+            const int e = c.tid, q = e >> 1, fl = e & 1;
+            const int sp = SP(cur)[q];
+            const float *aos = c.a(S) + sp * n;
+            const float v = fl ? (CPM(cur)[q] + aos[t]) + (1.0f - 2.0f * (float)CP(cur)[q]) * aos[0] : CPM(cur)[q];
+            cpm2[e] = v;
+        }
+        __syncthreads();
+        if (c.tid < 2 * L) {
+            const int e = c.tid, q = e >> 1, fl = e & 1;
+            const float v = cpm2[e];
+            int rank = 0;
+            for (int o = 0; o < 2 * L; o++) {
+                const float u = cpm2[o];
+                rank += (u < v || (u == v && o < e)) ? 1 : 0;
+            }
+            if (rank < L) {
+                SP(cur ^ 1)[rank] = SP(cur)[q];
+                CP(cur ^ 1)[rank] = CP(cur)[q] ^ fl;
+                CPM(cur ^ 1)[rank] = v;
+                FL(cur ^ 1)[rank] = FL(cur)[q] | ((uint64_t)fl << (t - 1));
+            }
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+    // codewords: hard decisions with the kept flips, o_0 set by Eq. (6)
+    uint32_t *xo = c.xb(S, SIDE);
+    for (int q = c.tid; q < L * W; q += kThreads) {
+        const int ql = q / W, wd = q % W;
+        const int sp = SP(cur)[ql];
+        const uint64_t flips = FL(cur)[ql];
+        const uint16_t *os = (const uint16_t *)(c.a(S - 1) + sp * (n / 2));
+        uint32_t word = hd[sp * W + wd];
+        for (int t = 1; t <= TAU; t++)
+            if ((flips >> (t - 1)) & 1u) {
+                const uint32_t o = os[t];
+                if ((int)(o >> 5) == wd)
+                    word ^= 1u << (o & 31);
+            }
+        const uint32_t o0 = os[0];
+        if ((int)(o0 >> 5) == wd) {
+            const uint32_t hd0 = (hd[sp * W + wd] >> (o0 & 31)) & 1u;
+            const uint32_t par = ((uint32_t)c.i(Ly::PAR)[sp] ^ (uint32_t)__popcll(flips) ^ hd0) & 1u;
+            word = (word & ~(1u << (o0 & 31))) | (par << (o0 & 31));
+        }
+        xo[q] = word;
+    }
+    if (c.tid < L) {
+        c.pm(S, SIDE)[c.tid] = CPM(cur)[c.tid];
+        c.anc(S, SIDE)[c.tid] = SP(cur)[c.tid];
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// internal node RM(R,S) (Alg. 2); V >= 0: depth on the leftmost spine
+// ---------------------------------------------------------------------------
+template <int M, int L, int R, int S, int V, int SIDE>
+__device__ void big_node(const BigCtx<M, L> &c, const float *pm_in);
+
+template <int M, int L, int R, int S, int V, int SIDE>
+__device__ __forceinline__ void big_child(const BigCtx<M, L> &c, const float *pm_in)
+{
+    if constexpr (R == 1)
+        fhtl_leaf<M, L, S, SIDE>(c, pm_in);
+    else if constexpr (R == S - 1)
+        spcl_leaf<M, L, S, SIDE>(c, pm_in);
+    else
+        big_node<M, L, R, S, V, SIDE>(c, pm_in);
+}
+
+template <int M, int L, int R, int S, int V, int SIDE>
+__device__ void big_node(const BigCtx<M, L> &c, const float *pm_in)
+{
+    using Ly = Lay<M, L>;
+    constexpr int n = 1 << S, h = n / 2, G = Ly::G;
+    static_assert(1 < R && R < S - 1, "internal node");
+    const bool perm = V >= 0 && c.pfht;
+    const int l = c.tid / G, lt = c.tid % G;
+    float *ach = c.a(S - 1); // children's LLRs: L rows of h
+    int *sel = c.sel(S);
+    int *orig = c.orig(S);
+    const float *pmL_in = pm_in;
+    if (perm) {
+        // LM of the 2L candidates: sum of |f| over the permuted LLRs of path cc mod L
+        constexpr int GH = G / 2;
+        const int cc = c.tid / GH, ct = c.tid % GH, src = cc % L;
+        MapR<S> mp;
+        load_map<S>(c.map(2 * L + 4 * L * (V >= 0 ? V : 0) + cc), mp);
+        float *scr = ach + cc * (h / 2);
+        for (int i = ct; i < h / 2; i += GH) {
+            const float v0 = fabsf(big_fminsum(in_llr<M, L, S>(c, src, apply_map<S>(mp, i)),
+                                               in_llr<M, L, S>(c, src, apply_map<S>(mp, i + h))));
+            const float v1 = fabsf(big_fminsum(in_llr<M, L, S>(c, src, apply_map<S>(mp, i + h / 2)),
+                                               in_llr<M, L, S>(c, src, apply_map<S>(mp, i + h / 2 + h))));
+            scr[i] = v0 + v1;
+        }
+        __syncthreads();
+        for (int wdt = h / 4; wdt >= 1; wdt /= 2) {
+            for (int i = ct; i < wdt; i += GH)
+                scr[i] = scr[i] + scr[i + wdt];
+            __syncthreads();
+        }
+        float *lm = c.f(Ly::SCR);
+        if (ct == 0)
+            lm[cc] = scr[0];
+        __syncthreads();
+        if (c.tid < 2 * L) {
+            const float v = lm[c.tid];
+            int rank = 0;
+            for (int o = 0; o < 2 * L; o++) {
+                const float u = lm[o];
+                rank += (u > v || (u == v && o < c.tid)) ? 1 : 0;
+            }
+            sel[rank] = c.tid;
+        }
+        __syncthreads();
+        if (c.tid < L) {
+            orig[c.tid] = sel[c.tid] % L;
+            c.ppm(S)[c.tid] = pm_in[sel[c.tid] % L];
+        }
+        __syncthreads();
+        pmL_in = c.ppm(S);
+    }
+    // f for the left child
+    {
+        MapR<S> mp;
+        int src = l;
+        if (perm) {
+            load_map<S>(c.map(2 * L + 4 * L * (V >= 0 ? V : 0) + sel[l]), mp);
+            src = orig[l];
+        }
+        for (int i = lt; i < h; i += G) {
+            const uint32_t i0 = perm ? apply_map<S>(mp, i) : (uint32_t)i;
+            const uint32_t i1 = perm ? apply_map<S>(mp, i + h) : (uint32_t)(i + h);
+            ach[l * h + i] = big_fminsum(in_llr<M, L, S>(c, src, i0), in_llr<M, L, S>(c, src, i1));
+        }
+    }
+    __syncthreads();
+    big_child<M, L, R - 1, S - 1, (V >= 0 ? V + 1 : -1), 0>(c, pmL_in);
+    // g for the right child, from the surviving ancestor's LLRs
+    {
+        const int k = c.anc(S - 1, 0)[l];
+        MapR<S> mp;
+        int src = k;
+        if (perm) {
+            load_map<S>(c.map(2 * L + 4 * L * (V >= 0 ? V : 0) + sel[k]), mp);
+            src = orig[k];
+        }
+        const uint32_t *xl = c.xb(S - 1, 0);
+        for (int i = lt; i < h; i += G) {
+            const uint32_t i0 = perm ? apply_map<S>(mp, i) : (uint32_t)i;
+            const uint32_t i1 = perm ? apply_map<S>(mp, i + h) : (uint32_t)(i + h);
+            ach[l * h + i] = big_g(in_llr<M, L, S>(c, src, i0), in_llr<M, L, S>(c, src, i1), get_bit<S - 1>(xl, l, i));
+        }
+    }
+    __syncthreads();
+    big_child<M, L, R, S - 1, -1, 1>(c, c.pm(S - 1, 0));
+    // combine (x_R ^ x_L, x_R), back through the node's permutation
+    {
+        const uint32_t *xl = c.xb(S - 1, 0);
+        const uint32_t *xr = c.xb(S - 1, 1);
+        uint32_t *xo = c.xb(S, SIDE);
+        constexpr int W = words_of(S);
+        for (int q = c.tid; q < L * W; q += kThreads) {
+            const int ql = q / W, wd = q % W;
+            const int k = c.anc(S - 1, 1)[ql];
+            const int a = c.anc(S - 1, 0)[k];
+            uint32_t word = 0;
+            if (perm) {
+                MapR<S> inv;
+                load_map<S>(c.map(2 * L + 4 * L * (V >= 0 ? V : 0) + 2 * L + sel[a]), inv);
+                for (int bt = 0; bt < cmin(32, n); bt++) {
+                    const uint32_t j = apply_map<S>(inv, (uint32_t)(wd * 32 + bt));
+                    const uint32_t bit = j < (uint32_t)h ? (get_bit<S - 1>(xr, ql, j) ^ get_bit<S - 1>(xl, k, j))
+                                                         : get_bit<S - 1>(xr, ql, j - h);
+                    word |= bit << bt;
+                }
+            } else {
+                for (int bt = 0; bt < cmin(32, n); bt++) {
+                    const uint32_t j = (uint32_t)(wd * 32 + bt);
+                    const uint32_t bit = j < (uint32_t)h ? (get_bit<S - 1>(xr, ql, j) ^ get_bit<S - 1>(xl, k, j))
+                                                         : get_bit<S - 1>(xr, ql, j - h);
+                    word |= bit << bt;
+                }
+            }
+            xo[q] = word;
+        }
+        if (c.tid < L) {
+            const int k = c.anc(S - 1, 1)[c.tid];
+            const int a = c.anc(S - 1, 0)[k];
+            c.anc(S, SIDE)[c.tid] = perm ? orig[a] : a;
+            c.pm(S, SIDE)[c.tid] = c.pm(S - 1, 1)[c.tid];
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the kernel: one workgroup per frame (grid-stride), P decoders per frame
+// ---------------------------------------------------------------------------
+template <int M, int R, int L>
+__global__ void __launch_bounds__(kThreads) rm_biglist_kernel(KernelArgs args)
+{
+    using Ly = Lay<M, L>;
+    constexpr int N = 1 << M;
+    extern __shared__ uint32_t big_smem[];
+    BigCtx<M, L> c;
+    c.w = big_smem;
+    c.tid = threadIdx.x;
+    c.pfht = args.pfht;
+    float *misc = c.f(Ly::MISC);
+    for (int64_t f = blockIdx.x; f < args.n_frames; f += gridDim.x) {
+        const uint32_t *fmaps = args.maps + f * args.frame_stride;
+        for (int i = c.tid; i < N; i += kThreads)
+            c.y()[i] = args.llr[f * N + i];
+        if (c.tid == 0)
+            misc[0] = __builtin_inff();
+        for (int i = c.tid; i < N / 32; i += kThreads)
+            c.w[Ly::BEST + i] = 0u;
+        __syncthreads();
+        for (int d = 0; d < args.P; d++) {
+            c.dmaps = fmaps + (size_t)d * args.maps_per_dec * kMapWords;
+            if (c.tid < L)
+                c.f(Ly::PM0)[c.tid] = (c.pfht || c.tid == 0) ? 0.0f : __builtin_inff();
+            __syncthreads();
+            big_node<M, L, R, M, 0, 0>(c, c.f(Ly::PM0));
+            // Alg. 5: first minimum over the list; replace only if strictly smaller
+            if (c.tid == 0) {
+                const float *pm = c.pm(M, 0);
+                int ls = 0;
+                for (int q = 1; q < L; q++)
+                    if (pm[q] < pm[ls])
+                        ls = q;
+                const int better = pm[ls] < misc[0];
+                if (better)
+                    misc[0] = pm[ls];
+                c.i(Ly::MISC)[1] = better;
+                c.i(Ly::MISC)[2] = ls;
+            }
+            __syncthreads();
+            // The root's codewords are in channel order already: with
+            // permutations the root's candidate maps include the initial
+            // maps, and without them the initial maps are the identity.
+            if (c.i(Ly::MISC)[1]) {
+                const int ls = c.i(Ly::MISC)[2];
+                const uint32_t *x = c.xb(M, 0);
+                for (int wd = c.tid; wd < N / 32; wd += kThreads)
+                    c.w[Ly::BEST + wd] = x[ls * (N / 32) + wd];
+            }
+            __syncthreads();
+        }
+        for (int i = c.tid; i < N / 32; i += kThreads)
+            ((uint32_t *)(args.out_bits + f * (N / 8)))[i] = c.w[Ly::BEST + i];
+        if (c.tid == 0 && args.out_pm)
+            args.out_pm[f] = misc[0];
+        __syncthreads();
+    }
+}
+
+} // namespace big
+} // namespace rmdec

@@ -239,8 +239,8 @@ std::vector<uint32_t> inverse_of(const std::vector<uint32_t> &q)
 
 const KernelEntry *find_kernel(int m, int r, int L)
 {
-    const KernelTable tabs[] = {kernels_codes_a(), kernels_codes_b(), kernels_codes_c(),
-                                kernels_codes_d(), kernels_codes_e(), kernels_codes_f()};
+    const KernelTable tabs[] = {kernels_codes_a(), kernels_codes_b(), kernels_codes_c(), kernels_codes_d(),
+                                kernels_codes_e(), kernels_codes_f(), kernels_codes_g()};
     for (const KernelTable &t : tabs)
         for (int i = 0; i < t.count; i++)
             if (t.entries[i].m == m && t.entries[i].r == r && t.entries[i].L == L)
@@ -256,8 +256,8 @@ int check_params(int m, int r, int P, int L, int perm_mode)
         return fail(RM_E_INVAL, "r must be in [1, m-1]");
     if (P < 1 || P > 1024)
         return fail(RM_E_INVAL, "P must be in [1, 1024]");
-    if (!(L == 1 || L == 2 || L == 4 || L == 8))
-        return fail(RM_E_INVAL, "L must be 1, 2, 4 or 8");
+    if (!(L == 1 || L == 2 || L == 4 || L == 8 || L == 16 || L == 32 || L == 64))
+        return fail(RM_E_INVAL, "L must be 1, 2, 4, 8, 16, 32 or 64");
     if (perm_mode != RM_PERM_NONE && perm_mode != RM_PERM_PFHT && perm_mode != RM_PERM_FRESH)
         return fail(RM_E_INVAL, "unknown perm_mode");
     return RM_OK;
@@ -400,17 +400,31 @@ rm_decoder *rm_decoder_create_ex(const rm_config *cfg)
         dec->table_bytes = (size_t)(chunk * per_frame);
     }
     int wpb = cfg->waves_per_block;
-    if (wpb == 0) {
-        wpb = 65536 / k->lds_bytes_per_wave;
-        wpb = wpb < 1 ? 1 : (wpb > 4 ? 4 : wpb);
-    }
-    if ((size_t)wpb * k->lds_bytes_per_wave > 65536) {
-        delete dec;
-        fail(RM_E_UNSUPPORTED, "LDS slice does not fit the requested waves per block");
-        return nullptr;
+    hipError_t e = hipGetDevice(&dec->device);
+    if (k->block_lds_bytes > 0) {
+        // one workgroup per frame: its LDS must fit the device's per-block limit
+        int lds_max = 0;
+        if (e == hipSuccess)
+            e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dec->device);
+        if (e == hipSuccess && (wpb > 1 || k->block_lds_bytes > lds_max)) {
+            delete dec;
+            fail(RM_E_UNSUPPORTED, wpb > 1 ? "lists of 16 or more paths run one frame per workgroup"
+                                           : "the list does not fit the device's LDS per workgroup");
+            return nullptr;
+        }
+        wpb = 1;
+    } else {
+        if (wpb == 0) {
+            wpb = 65536 / k->lds_bytes_per_wave;
+            wpb = wpb < 1 ? 1 : (wpb > 4 ? 4 : wpb);
+        }
+        if ((size_t)wpb * k->lds_bytes_per_wave > 65536) {
+            delete dec;
+            fail(RM_E_UNSUPPORTED, "LDS slice does not fit the requested waves per block");
+            return nullptr;
+        }
     }
     dec->cfg.waves_per_block = wpb;
-    hipError_t e = hipGetDevice(&dec->device);
     if (e == hipSuccess)
         e = hipMalloc((void **)&dec->d_maps, dec->table_bytes);
     if (e == hipSuccess && !fresh)
@@ -463,7 +477,8 @@ int rm_decoder_info(const rm_decoder *d, rm_info *out)
     out->n_perm_nodes = d->nperm;
     out->maps_per_decoder = d->maps_per_dec;
     out->waves_per_block = d->cfg.waves_per_block;
-    out->lds_bytes_per_wave = (size_t)d->kern->lds_bytes_per_wave;
+    out->lds_bytes_per_wave =
+        (size_t)(d->kern->block_lds_bytes > 0 ? d->kern->block_lds_bytes : d->kern->lds_bytes_per_wave);
     out->table_bytes = d->table_bytes;
     return RM_OK;
 }

@@ -16,6 +16,9 @@ struct KernelEntry {
     int lds_bytes_per_wave;
     int maps_per_dec; // maps stored per decoder in p-FHT mode
     LaunchFn launch;
+    // kernels that run one workgroup per frame (lists of 16 or more paths):
+    // the workgroup's LDS bytes; 0 for the one-wave-per-frame kernels
+    int block_lds_bytes = 0;
 };
 
 template <int M, int R, int L, int D, int WPE>
@@ -62,5 +65,6 @@ KernelTable kernels_codes_c();
 KernelTable kernels_codes_d();
 KernelTable kernels_codes_e();
 KernelTable kernels_codes_f();
+KernelTable kernels_codes_g(); // lists of 16, 32 and 64 paths
 
 } // namespace rmdec

@@ -76,7 +76,7 @@ def test_perm_draw_none_mode_is_identity():
 
 
 @pytest.mark.parametrize("args", [(2, 1, 1, 1), (11, 2, 1, 1), (7, 0, 1, 1), (7, 7, 1, 1), (7, 2, 0, 1),
-                                  (7, 2, 1025, 1), (7, 2, 1, 3), (7, 2, 1, 16)])
+                                  (7, 2, 1025, 1), (7, 2, 1, 3), (7, 2, 1, 12), (7, 2, 1, 128)])
 def test_invalid_parameters_rejected(args):
     m, r, P, L = args
     n, *_ = _lib.rm_perm_tables(m, r, P, L, 0, rmd.RM_PERM_PFHT, 64)
@@ -95,7 +95,8 @@ def test_small_cap_rejected():
 
 
 @pytest.mark.parametrize("m,r,L", [(7, 2, 1), (9, 2, 4), (9, 2, 1), (8, 3, 8), (8, 2, 4), (10, 2, 4), (5, 2, 2),
-                                   (6, 3, 8), (5, 1, 4), (4, 3, 1), (9, 3, 4), (9, 4, 8), (8, 4, 2)])
+                                   (6, 3, 8), (5, 1, 4), (4, 3, 1), (9, 3, 4), (9, 4, 8), (8, 4, 2),
+                                   (9, 4, 32), (8, 3, 64), (8, 2, 16), (9, 2, 32), (6, 2, 16)])
 def test_kernels_built_for_configs(m, r, L):
     assert rmd.rm_supported(m, r, L, rmd.RM_PERM_PFHT)
 

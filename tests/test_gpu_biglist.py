@@ -1,0 +1,114 @@
+"""Parity of the large-list kernels (L = 16, 32, 64: one workgroup per
+frame, the list in LDS) with the oracle, through the C ABI.
+
+Codewords must agree bit for bit and final metrics within 1e-5 relative,
+in the permuted, plain and fresh-permutation modes, on integer-valued LLRs
+(every tie-break rule) and on a larger sampled launch.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2108_12550_amd as rmd
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+NONE, PFHT, FRESH = rmd.RM_PERM_NONE, rmd.RM_PERM_PFHT, rmd.RM_PERM_FRESH
+THREADS = min(16, os.cpu_count() or 1)
+PM_RTOL = 1e-5
+BUILT = [(8, 2, 16), (8, 2, 32), (8, 2, 64), (8, 3, 16), (8, 3, 32), (8, 3, 64), (8, 4, 16), (8, 4, 32),
+         (8, 4, 64), (9, 2, 16), (9, 2, 32), (9, 3, 16), (9, 3, 32), (9, 4, 16), (9, 4, 32), (7, 2, 16),
+         (7, 3, 16), (6, 2, 16)]
+
+
+def gpu_decode(m, r, P, L, seed, mode, llr):
+    dec = rmd.Decoder(m, r, P, L, seed=seed, perm_mode=mode)
+    t = torch.from_numpy(np.ascontiguousarray(llr)).cuda()
+    bits, pm = dec.decode(t)
+    torch.cuda.synchronize()
+    out = bits.cpu().numpy(), pm.cpu().numpy()
+    dec.close()
+    return out
+
+
+def assert_parity(got, ref, label):
+    gb, gp = got
+    rb, rp = ref
+    bad = np.nonzero(np.any(gb != rb, axis=1))[0]
+    assert bad.size == 0, f"{label}: {bad.size} frames differ in bits, first {bad[:8]}"
+    rel = np.abs(gp.astype(np.float64) - rp) / np.maximum(1.0, np.abs(rp))
+    assert rel.max() <= PM_RTOL, f"{label}: metric rel diff {rel.max()}"
+
+
+def check(m, r, P, L, mode, llr, seed):
+    label = f"RM({r},{m}) P={P} L={L} mode={mode} seed={seed} n={llr.shape[0]}"
+    print("case", label, flush=True)
+    od = oracle.OracleDecoder(m, r, P, L, seed=seed, perm_mode=mode)
+    assert_parity(gpu_decode(m, r, P, L, seed, mode, llr), od.decode_batch(llr, n_threads=THREADS), label)
+
+
+@pytest.mark.parametrize("m,r,L", BUILT)
+def test_permuted_large_lists(m, r, L):
+    _, llr = synth.frames(m, r, 24, 2.0, seed=700 + m * 10 + r + L)
+    check(m, r, 2, L, PFHT, llr, seed=L + r)
+
+
+@pytest.mark.parametrize("m,r,L", [(9, 4, 32), (8, 3, 64), (9, 2, 16), (8, 2, 32), (8, 4, 64), (7, 3, 16)])
+def test_plain_large_lists(m, r, L):
+    """FHT-FSCL-L: one active path at the start, no permutations."""
+    _, llr = synth.frames(m, r, 30, 2.5, seed=800 + m * 10 + r + L)
+    check(m, r, 1, L, NONE, llr, seed=0)
+
+
+@pytest.mark.parametrize("m,r,P,L", [(9, 4, 2, 32), (8, 3, 1, 64), (9, 2, 3, 16)])
+def test_fresh_large_lists(m, r, P, L):
+    _, llr = synth.frames(m, r, 20, 2.0, seed=900 + m * 10 + r + L)
+    check(m, r, P, L, FRESH, llr, seed=5)
+
+
+@pytest.mark.parametrize("m,r,L", [(8, 3, 32), (9, 2, 16), (8, 4, 64), (6, 2, 16)])
+def test_integer_llr_ties_large_lists(m, r, L):
+    rng = np.random.default_rng(m * 1000 + L)
+    llr = rng.integers(-2, 3, size=(20, 1 << m)).astype(np.float32)
+    check(m, r, 2, L, PFHT, llr, seed=1)
+    check(m, r, 1, L, NONE, llr, seed=0)
+
+
+def test_all_zero_llr_large_list():
+    check(8, 3, 2, 32, PFHT, np.zeros((4, 256), np.float32), seed=2)
+
+
+def test_noiseless_large_list():
+    x, _ = synth.frames(9, 4, 16, 3.0, seed=9)
+    llr = (8.0 * (1.0 - 2.0 * x)).astype(np.float32)
+    bits, pm = gpu_decode(9, 4, 1, 32, 0, PFHT, llr)
+    assert np.array_equal(synth.unpack_bits(bits, 512), x)
+    assert np.all(pm == 0.0)
+
+
+def test_unbuilt_large_list_reported():
+    assert rmd.rm_supported(9, 4, 32, PFHT) == 1
+    assert rmd.rm_supported(9, 2, 64, PFHT) == 0  # 4*L*N bytes of LLRs exceed the LDS budget
+    assert rmd.rm_supported(10, 2, 32, PFHT) == 0
+
+
+def test_large_list_sampled_launch():
+    """RM(4,9) with L = 32 (Fig. 5(c)'s p-FHT-FSCL-32), 8192 frames in one
+    launch: every output a codeword, sampled frames against the oracle."""
+    n = 8192
+    _, llr = synth.frames(9, 4, n, 2.5, seed=77)
+    print("case sampled RM(4,9) P=1 L=32 n=8192", flush=True)
+    bits, pm = gpu_decode(9, 4, 1, 32, 0, PFHT, llr)
+    h = torch.from_numpy(synth.monomial_table(9, 9 - 4 - 1).astype(np.float32)).cuda()
+    xb = torch.from_numpy(synth.unpack_bits(bits, 512).astype(np.float32)).cuda()
+    assert int(torch.remainder(xb @ h.T, 2.0).sum().item()) == 0
+    idx = np.sort(np.random.default_rng(7).choice(n, 24, replace=False))
+    od = oracle.OracleDecoder(9, 4, 1, 32, seed=0)
+    assert_parity((bits[idx], pm[idx]), od.decode_batch(llr[idx], n_threads=THREADS), "sampled")
