@@ -152,6 +152,49 @@ __device__ __forceinline__ float in_llr(const BigCtx<M, L> &c, int l, uint32_t i
         return c.a(S)[l * (1 << S) + i];
 }
 
+// Of L sorted lists (row l: metric[l*mstride + j], j < K, non-decreasing)
+// keep the L smallest entries in the order (metric, l, j), as a stable merge
+// of the lists would: out_pm[q], out_src[q] = l and out_code[q] =
+// code[l*cstride + j] for q = 0..L-1 in that order.  A tournament in wave 0:
+// lane l holds the head of list l as the key (metric bits, l, j) (metrics
+// are non-negative, so their bit patterns order as the values do); L rounds
+// of a wave minimum each emit one entry and advance that list.
+template <int M, int L, int K>
+__device__ void select_smallest(const BigCtx<M, L> &c, const float *metric, int mstride, const uint16_t *code,
+                                int cstride, float *out_pm, int *out_src, int *out_code)
+{
+    static_assert(L <= kWave, "one lane per list");
+    if (c.tid < kWave) {
+        const int lane = c.tid;
+        auto key_at = [&](int j) {
+            return j < K ? ((uint64_t)__float_as_uint(metric[lane * mstride + j]) << 32) |
+                               ((uint64_t)lane << 16) | (uint64_t)j
+                         : ~0ull;
+        };
+        int ptr = 0;
+        uint64_t head = lane < L ? key_at(0) : ~0ull;
+        for (int q = 0; q < L; q++) {
+            uint64_t m = head;
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const uint64_t t = shfl_xor64(m, o);
+                m = t < m ? t : m;
+            }
+            const int wl = (int)((m >> 16) & 0xFFFFu), wj = (int)(m & 0xFFFFu);
+            if (lane == 0) {
+                out_pm[q] = __uint_as_float((uint32_t)(m >> 32));
+                out_src[q] = wl;
+                out_code[q] = (int)code[wl * cstride + wj];
+            }
+            if (lane == wl) {
+                ptr++;
+                head = key_at(ptr);
+            }
+        }
+    }
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // FHTL leaf RM(1,S) (Alg. 3, 4)
 // ---------------------------------------------------------------------------
@@ -165,14 +208,16 @@ __device__ void fhtl_leaf(const BigCtx<M, L> &c, const float *pm_in)
     const int l = c.tid / G, lt = c.tid % G;
     float *F = c.a(S) + l * n;
     float *scr = c.a(S - 1); // [L][h]: the sum of |alpha|
-    // Sum of |alpha| per path, halving tree
+    // Per path, in the path's own rows only (its G threads are one wave's
+    // lanes, so a wave-level sync orders the steps).
+    // Sum of |alpha|, halving tree
     for (int i = lt; i < h; i += G)
         scr[l * h + i] = fabsf(F[i]) + fabsf(F[i + h]);
-    __syncthreads();
+    wave_sync();
     for (int wdt = h / 2; wdt >= 1; wdt /= 2) {
         for (int i = lt; i < wdt; i += G)
             scr[l * h + i] = scr[l * h + i] + scr[l * h + i + wdt];
-        __syncthreads();
+        wave_sync();
     }
     // FHT, strides 2^{S-1} .. 1
     for (int t = 0; t < S; t++) {
@@ -183,7 +228,7 @@ __device__ void fhtl_leaf(const BigCtx<M, L> &c, const float *pm_in)
             F[i] = z - x;
             F[i + hh] = z + x;
         }
-        __syncthreads();
+        wave_sync();
     }
     // the path's elements in registers as keys: |F| bits, then the index
     // complemented (ties to the lower index), then the sign
@@ -201,7 +246,7 @@ __device__ void fhtl_leaf(const BigCtx<M, L> &c, const float *pm_in)
     }
     const float llr_abs = scr[l * h];
     const float pml = pm_in[l];
-    __syncthreads();
+    wave_sync();
     // K passes: the group's largest remaining key
     float *metric = F;                                   // [K] per path, in the path's own row
     uint16_t *cidx = (uint16_t *)(c.a(S - 1) + l * h); // [K] index << 1 | sign
@@ -233,44 +278,9 @@ __device__ void fhtl_leaf(const BigCtx<M, L> &c, const float *pm_in)
         }
     }
     __syncthreads();
-    // merge: rank of candidate (l, j) in the order (metric, l, j)
-    for (int q = c.tid; q < L * K; q += kThreads) {
-        const int ql = q / K, qj = q % K;
-        const float v = c.a(S)[ql * n + qj];
-        int rank = qj;
-        for (int o = 0; o < L; o++) {
-            if (o == ql)
-                continue;
-            const float *row = c.a(S) + o * n;
-            int lo = 0, hi = K; // entries before (v, ql): < v, or == v from a lower path
-            if (o < ql) {
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if (row[mid] <= v)
-                        lo = mid + 1;
-                    else
-                        hi = mid;
-                }
-            } else {
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if (row[mid] < v)
-                        lo = mid + 1;
-                    else
-                        hi = mid;
-                }
-            }
-            rank += lo;
-            if (rank >= L)
-                break;
-        }
-        if (rank < L) {
-            c.pm(S, SIDE)[rank] = v;
-            c.anc(S, SIDE)[rank] = ql;
-            c.i(Ly::SIDX)[rank] = (int)((const uint16_t *)(c.a(S - 1) + ql * h))[qj];
-        }
-    }
-    __syncthreads();
+    // merge: the L smallest of the L*K candidates in the order (metric, l, j)
+    select_smallest<M, L, K>(c, c.a(S), n, (const uint16_t *)c.a(S - 1), 2 * h, c.pm(S, SIDE), c.anc(S, SIDE),
+                             c.i(Ly::SIDX));
     // the survivors' codewords: bit j = sign ^ parity(~(i | j))
     uint32_t *xo = c.xb(S, SIDE);
     for (int q = c.tid; q < L * words_of(S); q += kThreads) {
@@ -367,35 +377,39 @@ __device__ void spcl_leaf(const BigCtx<M, L> &c, const float *pm_in)
         FL(0)[q] = 0;
     }
     __syncthreads();
+    // the TAU rounds in wave 0 (2L candidates, two per lane for L = 64)
     float *cpm2 = c.f(Ly::SCR); // [2L] candidate metrics
-    int cur = 0;
-    for (int t = 1; t <= TAU; t++) {
-        if (c.tid < 2 * L) {
-            const int e = c.tid, q = e >> 1, fl = e & 1;
-            const int sp = SP(cur)[q];
-            const float *aos = c.a(S) + sp * n;
-            const float v = fl ? (CPM(cur)[q] + aos[t]) + (1.0f - 2.0f * (float)CP(cur)[q]) * aos[0] : CPM(cur)[q];
-            cpm2[e] = v;
-        }
-        __syncthreads();
-        if (c.tid < 2 * L) {
-            const int e = c.tid, q = e >> 1, fl = e & 1;
-            const float v = cpm2[e];
-            int rank = 0;
-            for (int o = 0; o < 2 * L; o++) {
-                const float u = cpm2[o];
-                rank += (u < v || (u == v && o < e)) ? 1 : 0;
+    if (c.tid < kWave) {
+        int cur = 0;
+        for (int t = 1; t <= TAU; t++) {
+            for (int e = c.tid; e < 2 * L; e += kWave) {
+                const int q = e >> 1, fl = e & 1;
+                const int sp = SP(cur)[q];
+                const float *aos = c.a(S) + sp * n;
+                cpm2[e] = fl ? (CPM(cur)[q] + aos[t]) + (1.0f - 2.0f * (float)CP(cur)[q]) * aos[0] : CPM(cur)[q];
             }
-            if (rank < L) {
-                SP(cur ^ 1)[rank] = SP(cur)[q];
-                CP(cur ^ 1)[rank] = CP(cur)[q] ^ fl;
-                CPM(cur ^ 1)[rank] = v;
-                FL(cur ^ 1)[rank] = FL(cur)[q] | ((uint64_t)fl << (t - 1));
+            wave_sync();
+            for (int e = c.tid; e < 2 * L; e += kWave) {
+                const int q = e >> 1, fl = e & 1;
+                const float v = cpm2[e];
+                int rank = 0;
+                for (int o = 0; o < 2 * L; o++) {
+                    const float u = cpm2[o];
+                    rank += (u < v || (u == v && o < e)) ? 1 : 0;
+                }
+                if (rank < L) {
+                    SP(cur ^ 1)[rank] = SP(cur)[q];
+                    CP(cur ^ 1)[rank] = CP(cur)[q] ^ fl;
+                    CPM(cur ^ 1)[rank] = v;
+                    FL(cur ^ 1)[rank] = FL(cur)[q] | ((uint64_t)fl << (t - 1));
+                }
             }
+            wave_sync();
+            cur ^= 1;
         }
-        __syncthreads();
-        cur ^= 1;
     }
+    __syncthreads();
+    constexpr int cur = TAU & 1; // the state after TAU rounds
     // codewords: hard decisions with the kept flips, o_0 set by Eq. (6)
     uint32_t *xo = c.xb(S, SIDE);
     for (int q = c.tid; q < L * W; q += kThreads) {
@@ -468,11 +482,11 @@ __device__ void big_node(const BigCtx<M, L> &c, const float *pm_in)
                                                in_llr<M, L, S>(c, src, apply_map<S>(mp, i + h / 2 + h))));
             scr[i] = v0 + v1;
         }
-        __syncthreads();
+        wave_sync(); // a candidate's GH threads are lanes of one wave
         for (int wdt = h / 4; wdt >= 1; wdt /= 2) {
             for (int i = ct; i < wdt; i += GH)
                 scr[i] = scr[i] + scr[i + wdt];
-            __syncthreads();
+            wave_sync();
         }
         float *lm = c.f(Ly::SCR);
         if (ct == 0)

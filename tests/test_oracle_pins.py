@@ -362,6 +362,8 @@ def _fer(m, r, P, L, mode, ebn0, n, seed):
     ("FHT-FSCL-2", 2, "3.0", 6000),
     ("FHT-FSCL-4", 4, "3.0", 8000),
     ("FHT-FSCL-8", 8, "2.5", 6000),
+    ("FHT-FSCL-16", 16, "2.0", 2000),
+    ("FHT-FSCL-32", 32, "2.0", 3000),
 ])
 def test_plain_list_fer_matches_fig5(name, L, ebn0, n):
     """FHT-FSCL-L without permutations against its deterministic curves in
@@ -382,6 +384,9 @@ def test_plain_list_fer_matches_fig5(name, L, ebn0, n):
     ("p-FHT-FSC-1", oracle.PERM_FRESH, 1, "3.0", 12000),
     ("p-FHT-FSC-2", oracle.PERM_FRESH, 2, "2.5", 8000),
     ("p-FHT-FSCL-4", oracle.PERM_FRESH, 4, "2.5", 3000),
+    # large lists
+    ("p-FHT-FSCL-8", oracle.PERM_PFHT, 8, "2.0", 4000),
+    ("p-FHT-FSCL-16", oracle.PERM_PFHT, 16, "2.0", 6000),
 ])
 def test_fer_matches_fig5(name, mode, L, ebn0, n):
     pub = GOLDEN["fer_rm29"][name][ebn0]
@@ -397,6 +402,9 @@ def test_fer_matches_fig5(name, mode, L, ebn0, n):
     ("fer_rm49", 9, 4, "FHT-FSCL-4", oracle.PERM_NONE, 4, "4.0", 12000),
     ("fer_rm49", 9, 4, "p-FHT-FSC-2", oracle.PERM_PFHT, 2, "3.5", 5000),
     ("fer_rm49", 9, 4, "p-FHT-FSCL-4", oracle.PERM_PFHT, 4, "3.5", 12000),
+    ("fer_rm49", 9, 4, "FHT-FSCL-16", oracle.PERM_NONE, 16, "3.0", 2000),
+    ("fer_rm49", 9, 4, "FHT-FSCL-32", oracle.PERM_NONE, 32, "3.0", 2000),
+    ("fer_rm49", 9, 4, "p-FHT-FSCL-16", oracle.PERM_PFHT, 16, "3.0", 6000),
 ])
 def test_fer_matches_fig5_higher_orders(key, m, r, name, mode, L, ebn0, n):
     """RM(3,9) and RM(4,9) against Fig. 5(b) and 5(c): deeper permutation
