@@ -113,7 +113,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
-    ap.add_argument("--workload", choices=("rm29", "mixed", "serve"), default="rm29")
+    ap.add_argument("--workload", choices=("rm29", "mixed", "serve", "biglist"), default="rm29")
     ap.add_argument("--serve-ms", type=float, default=100.0, help="arrival window per rate of the serving trace")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving section of the rm29 workload")
     ap.add_argument("--fresh", action="store_true",
@@ -129,6 +129,8 @@ def main():
         return run_mixed(args)
     if args.workload == "serve":
         return run_serve(args)
+    if args.workload == "biglist":
+        return run_biglist(args)
 
     import torch
     import paper_2108_12550_amd as rmd
@@ -438,6 +440,71 @@ def run_serve(args):
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "serving loop: " + sv["workload"]}, "serving": sv,
            "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
+# --- large lists: one workgroup per frame ------------------------------------
+# RM(3,8) (N = 256, K = 93) with one p-FHT-FSCL-64 decoder, the p-FHT-FSCL-L
+# column of Table 5, whose normalised complexity is 5.2e5 operations per frame.
+BIG_CODE = (8, 3, 1, 64)  # (m, r, P, L)
+BIG_OPS = 5.2e5
+BIG_FRAMES = 32768
+BIG_KERNEL = "big::rm_biglist_kernel<8, 3, 64>"
+
+
+def run_biglist(args):
+    import torch
+    import oracle
+    import paper_2108_12550_amd as rmd
+    import synth
+    m, r, P, L = BIG_CODE
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = BIG_FRAMES
+    x, llr = synth.frames(m, r, n, 3.0, seed=31)
+    t = torch.from_numpy(llr).to(dev)
+    dec = rmd.Decoder(m, r, P, L, seed=SEED)
+    stream = torch.cuda.Stream(device=dev)
+    bits = torch.empty((n, (1 << m) // 8), dtype=torch.uint8, device=dev)
+    pm = torch.empty((n,), dtype=torch.float32, device=dev)
+    for _ in range(args.warmup):
+        dec.decode(t, out_bits=bits, out_metric=pm, stream=stream)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        dec.decode(t, out_bits=bits, out_metric=pm, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / max(1, args.steps)
+    fps = n / (ms / 1e3)
+    xb = synth.unpack_bits(bits.cpu().numpy(), 1 << m)
+    fer = fer_ci(int(np.any(xb != x, axis=1).sum()), n)
+    achieved = BIG_OPS * fps / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(ALU_PEAK_TOPS, 4), "unit": "TFLOP/s",
+            "frac": round(achieved / ALU_PEAK_TOPS, 5), "traffic": None, "kernel": BIG_KERNEL,
+            "avg_launch_ms": round(ms, 4), "hbm_gbs_algorithmic": round((4 * 256 + 32 + 4) * fps / 1e9, 3)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = min(16, os.cpu_count() or 1)
+        od = oracle.OracleDecoder(m, r, P, L, seed=SEED)
+        done, same, t0 = 0, True, time.perf_counter()
+        gb = bits.cpu().numpy()
+        while done < n and time.perf_counter() - t0 < args.cpu_budget:
+            sl = slice(done, min(done + 16 * threads, n))
+            ob, _ = od.decode_batch(llr[sl], n_threads=threads, frame0=sl.start)
+            same &= bool(np.array_equal(ob, gb[sl]))
+            done = sl.stop
+        dt = time.perf_counter() - t0
+        cpu = {"value": done / dt, "unit": "frames/s", "cores": threads, "kind": "oracle",
+               "sample": f"first {done} frames ({dt:.1f} s), {threads} threads, bit-exact vs GPU: {same}"}
+    out = {"metric": METRIC, "value": round(fps, 1), "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "RM(8,3) N=256 K=93 (paper's RM(3,8)), one p-FHT-FSCL decoder with L=64 "
+                                  "(Table 5, p-FHT-FSCL-L), BPSK/AWGN Eb/N0 3.0 dB", "frames_per_step": n},
+           "fer": {"3.0": fer}, "roofline": roof, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 
 

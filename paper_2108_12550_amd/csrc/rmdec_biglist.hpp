@@ -56,7 +56,7 @@ struct Lay {
     static constexpr int SEL = ANC + (M + 1) * 2 * L; // [M+1][2L]
     static constexpr int ORIG = SEL + (M + 1) * 2 * L; // [M+1][L]
     static constexpr int PPM = ORIG + (M + 1) * L;     // [M+1][L]
-    static constexpr int SCR = PPM + (M + 1) * L;      // 2L floats: LM values, SPC candidate metrics
+    static constexpr int SCR = (PPM + (M + 1) * L + 3) & ~3; // 2L floats (16-byte aligned): LM values, SPC candidate metrics
     static constexpr int PM0 = SCR + 2 * L;            // L: the root's input metrics
     static constexpr int SIDX = PM0 + L;               // L: FHT survivors' index and sign
     static constexpr int PAR = SIDX + L;               // L: SPC parities of the input paths
@@ -106,11 +106,17 @@ __device__ __forceinline__ float big_fminsum(float a, float b)
 }
 __device__ __forceinline__ float big_g(float a, float b, uint32_t c) { return b + (1.0f - 2.0f * (float)c) * a; }
 
-__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int o)
+// largest / smallest 64-bit key over aligned groups of G lanes (DPP and
+// swizzle butterflies)
+template <int G>
+__device__ __forceinline__ uint64_t group_umax(uint64_t v)
 {
-    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, o);
-    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), o);
-    return ((uint64_t)hi << 32) | lo;
+    return bfly_umax<G / 2>(v);
+}
+template <int G>
+__device__ __forceinline__ uint64_t group_umin(uint64_t v)
+{
+    return ~bfly_umax<G / 2>(~v);
 }
 
 template <int M, int L>
@@ -167,19 +173,14 @@ __device__ void select_smallest(const BigCtx<M, L> &c, const float *metric, int 
     if (c.tid < kWave) {
         const int lane = c.tid;
         auto key_at = [&](int j) {
-            return j < K ? ((uint64_t)__float_as_uint(metric[lane * mstride + j]) << 32) |
-                               ((uint64_t)lane << 16) | (uint64_t)j
-                         : ~0ull;
+            return (lane < L && j < K) ? ((uint64_t)__float_as_uint(metric[lane * mstride + j]) << 32) |
+                                             ((uint64_t)lane << 16) | (uint64_t)j
+                                       : ~0ull;
         };
         int ptr = 0;
-        uint64_t head = lane < L ? key_at(0) : ~0ull;
+        uint64_t head = key_at(0), next = key_at(1); // the next entry is loaded a round ahead
         for (int q = 0; q < L; q++) {
-            uint64_t m = head;
-#pragma unroll
-            for (int o = 1; o < kWave; o <<= 1) {
-                const uint64_t t = shfl_xor64(m, o);
-                m = t < m ? t : m;
-            }
+            const uint64_t m = group_umin<kWave>(head);
             const int wl = (int)((m >> 16) & 0xFFFFu), wj = (int)(m & 0xFFFFu);
             if (lane == 0) {
                 out_pm[q] = __uint_as_float((uint32_t)(m >> 32));
@@ -188,7 +189,8 @@ __device__ void select_smallest(const BigCtx<M, L> &c, const float *metric, int 
             }
             if (lane == wl) {
                 ptr++;
-                head = key_at(ptr);
+                head = next;
+                next = key_at(ptr + 1);
             }
         }
     }
@@ -259,11 +261,7 @@ __device__ void fhtl_leaf(const BigCtx<M, L> &c, const float *pm_in)
                 b = key[e];
                 be = e;
             }
-        uint64_t gb = b;
-        for (int o = 1; o < G; o <<= 1) {
-            const uint64_t t = shfl_xor64(gb, o);
-            gb = t > gb ? t : gb;
-        }
+        const uint64_t gb = group_umax<G>(b);
         if (be >= 0 && gb == b) {
 #pragma unroll
             for (int e = 0; e < E; e++)
@@ -345,11 +343,7 @@ __device__ void spcl_leaf(const BigCtx<M, L> &c, const float *pm_in)
                 b = key[e];
                 be = e;
             }
-        uint64_t gb = b;
-        for (int o = 1; o < G; o <<= 1) {
-            const uint64_t x = shfl_xor64(gb, o);
-            gb = x < gb ? x : gb;
-        }
+        const uint64_t gb = group_umin<G>(b);
         if (be >= 0 && gb == b) {
 #pragma unroll
             for (int e = 0; e < E; e++)
@@ -393,9 +387,15 @@ __device__ void spcl_leaf(const BigCtx<M, L> &c, const float *pm_in)
                 const int q = e >> 1, fl = e & 1;
                 const float v = cpm2[e];
                 int rank = 0;
-                for (int o = 0; o < 2 * L; o++) {
-                    const float u = cpm2[o];
-                    rank += (u < v || (u == v && o < e)) ? 1 : 0;
+                const float4 *c4 = (const float4 *)cpm2;
+#pragma unroll
+                for (int o4 = 0; o4 < 2 * L / 4; o4++) {
+                    const float4 u = c4[o4];
+                    const int o = 4 * o4;
+                    rank += (u.x < v || (u.x == v && o < e)) ? 1 : 0;
+                    rank += (u.y < v || (u.y == v && o + 1 < e)) ? 1 : 0;
+                    rank += (u.z < v || (u.z == v && o + 2 < e)) ? 1 : 0;
+                    rank += (u.w < v || (u.w == v && o + 3 < e)) ? 1 : 0;
                 }
                 if (rank < L) {
                     SP(cur ^ 1)[rank] = SP(cur)[q];
@@ -591,7 +591,7 @@ __global__ void __launch_bounds__(kThreads) rm_biglist_kernel(KernelArgs args)
 {
     using Ly = Lay<M, L>;
     constexpr int N = 1 << M;
-    extern __shared__ uint32_t big_smem[];
+    extern __shared__ __align__(16) uint32_t big_smem[];
     BigCtx<M, L> c;
     c.w = big_smem;
     c.tid = threadIdx.x;
