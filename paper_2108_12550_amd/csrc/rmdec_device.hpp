@@ -483,6 +483,64 @@ __device__ __forceinline__ float tree_sum(float (&v)[RR])
 }
 
 // FHT butterflies (Alg. 4): stride h = 2^{s-1} .. 1, (lo, hi) <- (hi - lo, hi + lo)
+// f = f + c * (f of the partner lane at XOR distance H), one v_fmac_f32
+// with a DPP operand (H = 4: row_half_mirror, then quad_perm [3,2,1,0] on
+// the mirrored copy, i.e. lane ^ 7 ^ 3).  NOP: start with two wait states
+// (the source may have been written by the instruction just before).
+#define RM_DPP_MASKS " row_mask:0xf bank_mask:0xf bound_ctrl:1"
+template <int H, bool NOP>
+__device__ __forceinline__ void fmac_dpp(float &f, float c)
+{
+    if constexpr (H == 1) {
+        if constexpr (NOP)
+            asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %0, %1 quad_perm:[1,0,3,2]" RM_DPP_MASKS : "+v"(f) : "v"(c));
+        else
+            asm volatile("v_fmac_f32_dpp %0, %0, %1 quad_perm:[1,0,3,2]" RM_DPP_MASKS : "+v"(f) : "v"(c));
+    } else if constexpr (H == 2) {
+        if constexpr (NOP)
+            asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %0, %1 quad_perm:[2,3,0,1]" RM_DPP_MASKS : "+v"(f) : "v"(c));
+        else
+            asm volatile("v_fmac_f32_dpp %0, %0, %1 quad_perm:[2,3,0,1]" RM_DPP_MASKS : "+v"(f) : "v"(c));
+    } else if constexpr (H == 8) {
+        if constexpr (NOP)
+            asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %0, %1 row_ror:8" RM_DPP_MASKS : "+v"(f) : "v"(c));
+        else
+            asm volatile("v_fmac_f32_dpp %0, %0, %1 row_ror:8" RM_DPP_MASKS : "+v"(f) : "v"(c));
+    } else {
+        static_assert(H == 4, "one or two DPP moves");
+        float t;
+        asm volatile("s_nop 1\n\t"
+                     "v_mov_b32_dpp %1, %0 row_half_mirror" RM_DPP_MASKS "\n\t"
+                     "s_nop 1\n\t"
+                     "v_fmac_f32_dpp %0, %1, %2 quad_perm:[3,2,1,0]" RM_DPP_MASKS
+                     : "+v"(f), "=&v"(t)
+                     : "v"(c));
+    }
+}
+// two elements at H = 4, the second mirror move filling the first's wait state
+template <bool NOP>
+__device__ __forceinline__ void fmac_dpp_pair4(float &f0, float &f1, float c)
+{
+    float t0, t1;
+    if constexpr (NOP)
+        asm volatile("s_nop 1\n\t"
+                     "v_mov_b32_dpp %2, %0 row_half_mirror" RM_DPP_MASKS "\n\t"
+                     "v_mov_b32_dpp %3, %1 row_half_mirror" RM_DPP_MASKS "\n\t"
+                     "s_nop 0\n\t"
+                     "v_fmac_f32_dpp %0, %2, %4 quad_perm:[3,2,1,0]" RM_DPP_MASKS "\n\t"
+                     "v_fmac_f32_dpp %1, %3, %4 quad_perm:[3,2,1,0]" RM_DPP_MASKS
+                     : "+v"(f0), "+v"(f1), "=&v"(t0), "=&v"(t1)
+                     : "v"(c));
+    else
+        asm volatile("v_mov_b32_dpp %2, %0 row_half_mirror" RM_DPP_MASKS "\n\t"
+                     "v_mov_b32_dpp %3, %1 row_half_mirror" RM_DPP_MASKS "\n\t"
+                     "s_nop 0\n\t"
+                     "v_fmac_f32_dpp %0, %2, %4 quad_perm:[3,2,1,0]" RM_DPP_MASKS "\n\t"
+                     "v_fmac_f32_dpp %1, %3, %4 quad_perm:[3,2,1,0]" RM_DPP_MASKS
+                     : "+v"(f0), "+v"(f1), "=&v"(t0), "=&v"(t1)
+                     : "v"(c));
+}
+
 template <int H, int G, int RR>
 __device__ __forceinline__ void fht_stages(float (&F)[RR], int lg)
 {
@@ -496,6 +554,35 @@ __device__ __forceinline__ void fht_stages(float (&F)[RR], int lg)
                     F[j] = hi - lo;
                     F[j + hj] = hi + lo;
                 }
+        } else if constexpr (H == 1 || H == 2 || H == 4 || H == 8) {
+            // F = F + c * partner, one v_fmac_f32 with a DPP operand: c = +1
+            // in the upper lane (hi + lo), -1 in the lower (lo - hi, the
+            // difference negated; exact in magnitude, since the product by
+            // +-1 is exact and the sum is rounded once).  The partners of a
+            // stage always carry the same sign, so after the stages lane lg
+            // holds F times (-1)^(number of zero bits of lg among the
+            // cross-lane strides); fht_true_sign restores the sign of the
+            // selected entries.  A DPP read must not follow the VALU write of
+            // its source by fewer than two wait states.  In the first
+            // cross-lane stage the sources were written by compiled code,
+            // which may be scheduled right before the statement, so each
+            // statement starts with an s_nop; later stages read values their
+            // predecessor statement wrote at least two statements earlier
+            // (the statements are volatile, hence in order), unless a lane
+            // holds fewer than three elements.
+            constexpr bool NOP = (H == G / 2) || RR < 3;
+            const float cf = (lg & H) ? 1.0f : -1.0f;
+            if constexpr (H == 4) {
+#pragma unroll
+                for (int j = 0; j + 1 < RR; j += 2)
+                    fmac_dpp_pair4<NOP>(F[j], F[j + 1], cf);
+                if constexpr (RR % 2 == 1)
+                    fmac_dpp<4, true>(F[RR - 1], cf);
+            } else {
+#pragma unroll
+                for (int j = 0; j < RR; j++)
+                    fmac_dpp<H, NOP>(F[j], cf);
+            }
         } else {
             // lower lane: partner - self = hi - lo; upper lane: partner + self = lo + hi
             const uint32_t neg = (lg & H) ? 0u : 0x80000000u;
@@ -545,6 +632,19 @@ __device__ __forceinline__ uint32_t fht_jcode(int j)
 __device__ __forceinline__ double key_or_lo(double k, uint32_t bits)
 {
     return __longlong_as_double((long long)((uint64_t)__double_as_longlong(k) | bits));
+}
+// [F < 0] for a selected key (its low bit holds the sign bit of the stored
+// F): F was stored times the sign of its lane lg (the cross-lane FHT stages
+// of strides in XM, 1 to 8, leave lane lg negated once for every zero bit of
+// lg among them); a zero F counts as not negative, as the comparison F < 0
+// has it.
+template <int G, uint32_t XM>
+__device__ __forceinline__ uint32_t fht_true_sign(uint64_t kb)
+{
+    const uint32_t fb = (uint32_t)(kb >> 32);
+    const uint32_t lgw = (uint32_t)(G - 1) - (((uint32_t)kb >> 1) & (uint32_t)(G - 1));
+    const uint32_t sneg = (uint32_t)__popc(~lgw & XM) & 1u;
+    return (fb & 0x7FFFFFFFu) ? (((uint32_t)kb & 1u) ^ sneg) : 0u;
 }
 // max/min of |a| and b (b non-negative)
 __device__ __forceinline__ double dmax_abs(double b, double a)
@@ -598,6 +698,8 @@ __device__ __forceinline__ NodeRes<(1 << S), kWave / (L * D)> fhtl(const Ctx<M, 
     fht_stages<n / 2, G, RR>(A, lg);
 
     const uint32_t lanebits = (uint32_t)(G - 1 - lg) << 1;
+    // cross-lane strides of this node's FHT done as v_fmac with a DPP operand
+    constexpr uint32_t XM = (uint32_t)((G < n ? G : n) - 1) & 15u;
     float mypm;       // metric of this lane's candidate (Eq. (10))
     uint32_t myinf;   // its index code and sign
     int cand;         // its position t in the path's candidate order
@@ -611,7 +713,7 @@ __device__ __forceinline__ NodeRes<(1 << S), kWave / (L * D)> fhtl(const Ctx<M, 
         cand = valid ? rank : lg;
         const uint64_t kb = (uint64_t)__double_as_longlong(k);
         mypm = pm + 0.5f * (sabs - fabsf(__uint_as_float((uint32_t)(kb >> 32))));
-        myinf = (uint32_t)kb & 0xFFFu;
+        myinf = ((uint32_t)kb & 0xFFEu) | fht_true_sign<G, XM>(kb);
     } else {
         // lane-local three largest keys (without lane bits: one lane, one lg)
         double b1 = 0.0, b2 = 0.0, b3 = 0.0;
@@ -674,7 +776,7 @@ __device__ __forceinline__ NodeRes<(1 << S), kWave / (L * D)> fhtl(const Ctx<M, 
         // the candidate's metric (Eq. (10)) and its index and sign
         const uint64_t kb = (uint64_t)__double_as_longlong(mykey);
         mypm = pm + 0.5f * (sabs - __uint_as_float((uint32_t)(kb >> 32)));
-        myinf = (uint32_t)kb & 0xFFFu;
+        myinf = ((uint32_t)kb & 0xFFEu) | fht_true_sign<G, XM>(kb);
         cand = lg;
     }
 
