@@ -158,6 +158,49 @@ __device__ __forceinline__ float in_llr(const BigCtx<M, L> &c, int l, uint32_t i
         return c.a(S)[l * (1 << S) + i];
 }
 
+// Ascending bitonic sort of NK = 2^k distinct 64-bit keys held by wave 0:
+// element i = lane + 64 r sits in register r (two registers for NK = 128);
+// afterwards element i holds the key of rank i.  Lanes past NK hold keys of
+// their own (sorted among themselves, never mixed with the NK).
+template <int NK>
+using WaveKeys = uint64_t[NK > kWave ? 2 : 1];
+
+template <int NK, int SZ, int D>
+__device__ __forceinline__ void wave_sort_stage(WaveKeys<NK> &k, int lane)
+{
+    constexpr int NR = NK > kWave ? 2 : 1;
+    if constexpr (D == kWave) {
+        // between the two registers of a lane (the final merge of 128)
+        const uint64_t a = k[0], b = k[1];
+        k[0] = a < b ? a : b;
+        k[1] = a < b ? b : a;
+    } else {
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            const uint64_t o = xor_lanes<D>(k[r]);
+            const int i = lane + kWave * r;
+            const bool asc = SZ >= NK || (i & SZ) == 0;
+            const bool takemin = ((i & D) == 0) == asc;
+            const bool less = k[r] < o;
+            k[r] = (less == takemin) ? k[r] : o;
+        }
+    }
+}
+template <int NK, int SZ, int D>
+__device__ __forceinline__ void wave_sort_run(WaveKeys<NK> &k, int lane)
+{
+    wave_sort_stage<NK, SZ, D>(k, lane);
+    if constexpr (D > 1)
+        wave_sort_run<NK, SZ, D / 2>(k, lane);
+    else if constexpr (SZ < NK)
+        wave_sort_run<NK, SZ * 2, SZ>(k, lane);
+}
+template <int NK>
+__device__ __forceinline__ void wave_sort(WaveKeys<NK> &k, int lane)
+{
+    wave_sort_run<NK, 2, 1>(k, lane);
+}
+
 // Of L sorted lists (row l: metric[l*mstride + j], j < K, non-decreasing)
 // keep the L smallest entries in the order (metric, l, j), as a stable merge
 // of the lists would: out_pm[q], out_src[q] = l and out_code[q] =
@@ -371,36 +414,41 @@ __device__ void spcl_leaf(const BigCtx<M, L> &c, const float *pm_in)
         FL(0)[q] = 0;
     }
     __syncthreads();
-    // the TAU rounds in wave 0 (2L candidates, two per lane for L = 64)
-    float *cpm2 = c.f(Ly::SCR); // [2L] candidate metrics
+    // the TAU rounds in wave 0: the 2L candidates (keep 2q, flip 2q+1) as
+    // keys (metric bits, enumeration position), sorted over the lanes; rank
+    // r < L becomes list entry r.  Metrics are non-negative (the flip adds
+    // |alpha_{o_t}| >= |alpha_{o_0}| before subtracting |alpha_{o_0}|), so
+    // their bit patterns order as the values do.
     if (c.tid < kWave) {
+        constexpr int NK = 2 * L;
+        constexpr int NR = NK > kWave ? 2 : 1;
+        const int lane = c.tid;
         int cur = 0;
         for (int t = 1; t <= TAU; t++) {
-            for (int e = c.tid; e < 2 * L; e += kWave) {
-                const int q = e >> 1, fl = e & 1;
-                const int sp = SP(cur)[q];
-                const float *aos = c.a(S) + sp * n;
-                cpm2[e] = fl ? (CPM(cur)[q] + aos[t]) + (1.0f - 2.0f * (float)CP(cur)[q]) * aos[0] : CPM(cur)[q];
-            }
-            wave_sync();
-            for (int e = c.tid; e < 2 * L; e += kWave) {
-                const int q = e >> 1, fl = e & 1;
-                const float v = cpm2[e];
-                int rank = 0;
-                const float4 *c4 = (const float4 *)cpm2;
+            WaveKeys<NK> key;
 #pragma unroll
-                for (int o4 = 0; o4 < 2 * L / 4; o4++) {
-                    const float4 u = c4[o4];
-                    const int o = 4 * o4;
-                    rank += (u.x < v || (u.x == v && o < e)) ? 1 : 0;
-                    rank += (u.y < v || (u.y == v && o + 1 < e)) ? 1 : 0;
-                    rank += (u.z < v || (u.z == v && o + 2 < e)) ? 1 : 0;
-                    rank += (u.w < v || (u.w == v && o + 3 < e)) ? 1 : 0;
+            for (int r = 0; r < NR; r++) {
+                const int e = lane + kWave * r;
+                if (e < 2 * L) {
+                    const int q = e >> 1, fl = e & 1;
+                    const int sp = SP(cur)[q];
+                    const float *aos = c.a(S) + sp * n;
+                    const float v =
+                        fl ? (CPM(cur)[q] + aos[t]) + (1.0f - 2.0f * (float)CP(cur)[q]) * aos[0] : CPM(cur)[q];
+                    key[r] = ((uint64_t)__float_as_uint(v) << 32) | (uint32_t)e;
+                } else {
+                    key[r] = ~0ull;
                 }
+            }
+            wave_sort<NK>(key, lane);
+#pragma unroll
+            for (int r = 0; r < NR; r++) {
+                const int rank = lane + kWave * r;
                 if (rank < L) {
+                    const int e = (int)(key[r] & 0xFFFFu), q = e >> 1, fl = e & 1;
                     SP(cur ^ 1)[rank] = SP(cur)[q];
                     CP(cur ^ 1)[rank] = CP(cur)[q] ^ fl;
-                    CPM(cur ^ 1)[rank] = v;
+                    CPM(cur ^ 1)[rank] = __uint_as_float((uint32_t)(key[r] >> 32));
                     FL(cur ^ 1)[rank] = FL(cur)[q] | ((uint64_t)fl << (t - 1));
                 }
             }
