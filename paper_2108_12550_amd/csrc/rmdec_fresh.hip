@@ -58,83 +58,60 @@ __device__ __forceinline__ uint32_t apply(const uint32_t (&col)[kDim], uint32_t 
     return y;
 }
 
-// Gauss-Jordan elimination over F2 on [A | I] (rows of A in the low bits,
-// identity at bit 16 + j).  Pivot for column c: the lowest unused row with
-// bit c.  False if A is singular; else inv[c] = row c of A^{-1}, taken from
-// the row whose left part ends as e_c.
-__device__ __forceinline__ bool invert(const uint32_t (&row)[kDim], int md, uint32_t (&inv)[kDim])
-{
-    uint32_t t[kDim];
-#pragma unroll
-    for (int j = 0; j < kDim; j++)
-        t[j] = row[j] | (1u << (16 + j));
-    uint32_t used = 0;
-#pragma unroll
-    for (int c = 0; c < kDim; c++) {
-        if (c < md) {
-            uint32_t pv = 0;
-            int pj = -1;
-#pragma unroll
-            for (int j = kDim - 1; j >= 0; j--)
-                if (((t[j] >> c) & 1u) && !((used >> j) & 1u)) {
-                    pv = t[j];
-                    pj = j;
-                }
-            if (pj < 0)
-                return false;
-            used |= 1u << pj;
-#pragma unroll
-            for (int j = 0; j < kDim; j++)
-                if (j != pj && ((t[j] >> c) & 1u))
-                    t[j] ^= pv;
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < kDim; c++) {
-        uint32_t w = 0;
-#pragma unroll
-        for (int j = 0; j < kDim; j++)
-            w |= (t[j] & 0xFFFFu) == (1u << c) ? t[j] >> 16 : 0u;
-        inv[c] = w;
-    }
-    return true;
-}
-
 // one uniform element of AGL(md, 2) and its inverse, built row by row: row k
 // of A (low md bits of one output) is redrawn until it lies outside the span
 // of rows 0..k-1, then b.  Independence is tested by reducing the candidate
 // against an XOR basis indexed by leading bit.  One loop trip per drawn
 // candidate, whichever row it is for, so that the lanes of a wave diverge
 // only by their total number of redraws.
+//
+// Each basis vector also records which rows it is the sum of (comb, a mask
+// over row indices).  Once all md rows are in, reducing the basis to the
+// identity (clearing bit h of every higher vector with vector h, in
+// increasing h) leaves comb[h] = the rows that sum to e_h, i.e. row h of
+// A^{-1} (C A = I for the matrix C of the comb rows).
 __device__ __forceinline__ void draw_map(int md, uint64_t &st, CMap &a, CMap &ai)
 {
     const uint32_t mask = (1u << md) - 1u;
-    uint32_t row[kDim], basis[kDim], inv[kDim];
+    uint32_t row[kDim], basis[kDim], comb[kDim];
 #pragma unroll
     for (int j = 0; j < kDim; j++) {
         row[j] = 0;
         basis[j] = 0;
+        comb[j] = 0;
     }
     for (int k = 0; k < md;) {
         const uint32_t r = (uint32_t)(smx_next(st) & mask);
-        uint32_t x = r;
+        uint32_t x = r, cx = 1u << k;
 #pragma unroll
-        for (int h = kDim - 1; h >= 0; h--)
-            x ^= ((x >> h) & 1u) ? basis[h] : 0u;
+        for (int h = kDim - 1; h >= 0; h--) {
+            const bool hit = (x >> h) & 1u;
+            x ^= hit ? basis[h] : 0u;
+            cx ^= hit ? comb[h] : 0u;
+        }
         if (x) {
             const int lead = 31 - __builtin_clz(x);
 #pragma unroll
             for (int j = 0; j < kDim; j++) {
                 basis[j] = j == lead ? x : basis[j];
+                comb[j] = j == lead ? cx : comb[j];
                 row[j] = j == k ? r : row[j];
             }
             k++;
         }
     }
     a.b = (uint32_t)(smx_next(st) & mask);
-    invert(row, md, inv); // A is invertible by construction
+    // reduce the basis (vector h has leading bit h) to the identity
+#pragma unroll
+    for (int h = 0; h < kDim; h++)
+#pragma unroll
+        for (int h2 = h + 1; h2 < kDim; h2++) {
+            const bool hit = (basis[h2] >> h) & 1u;
+            basis[h2] ^= hit ? basis[h] : 0u;
+            comb[h2] ^= hit ? comb[h] : 0u;
+        }
     transpose(row, a.col);
-    transpose(inv, ai.col);
+    transpose(comb, ai.col); // comb[h] is row h of A^{-1}
     ai.b = apply(ai.col, a.b); // p^{-1}(y) = A^{-1} y + A^{-1} b
 }
 
