@@ -56,7 +56,7 @@ struct Lay {
     static constexpr int SEL = ANC + (M + 1) * 2 * L; // [M+1][2L]
     static constexpr int ORIG = SEL + (M + 1) * 2 * L; // [M+1][L]
     static constexpr int PPM = ORIG + (M + 1) * L;     // [M+1][L]
-    static constexpr int SCR = (PPM + (M + 1) * L + 3) & ~3; // 2L floats (16-byte aligned): LM values, SPC candidate metrics
+    static constexpr int SCR = PPM + (M + 1) * L;      // 2L floats: the candidates' LM values
     static constexpr int PM0 = SCR + 2 * L;            // L: the root's input metrics
     static constexpr int SIDX = PM0 + L;               // L: FHT survivors' index and sign
     static constexpr int PAR = SIDX + L;               // L: SPC parities of the input paths
