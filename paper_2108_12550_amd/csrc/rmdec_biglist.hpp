@@ -22,11 +22,13 @@
 #include <stdint.h>
 
 #include "rmdec_device.hpp"
+#include "rmdec_kernels.hpp"
 
 namespace rmdec {
 namespace big {
 
 constexpr int kThreads = 512;
+constexpr int kMaxPerm = 4; // permutation-domain nodes on the spine (r - 1 for RM(r, m), r <= 5)
 
 __host__ __device__ constexpr int words_of(int s) { return s >= 5 ? (1 << (s - 5)) : 1; }
 __host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
@@ -48,15 +50,16 @@ struct Lay {
         return w;
     }
     static constexpr int XB = A_END;
-    static constexpr int XB_END = XB + xb_below(M + 1);
-    // per level s: metrics and ancestors of both children's outputs
-    static constexpr int PM = XB_END;            // [M+1][2][L] floats
-    static constexpr int ANC = PM + (M + 1) * 2 * L; // [M+1][2][L] ints
-    // per permutation-domain node (by level): kept candidates, their source path and metric
-    static constexpr int SEL = ANC + (M + 1) * 2 * L; // [M+1][2L]
-    static constexpr int ORIG = SEL + (M + 1) * 2 * L; // [M+1][L]
-    static constexpr int PPM = ORIG + (M + 1) * L;     // [M+1][L]
-    static constexpr int SCR = PPM + (M + 1) * L;      // 2L floats: the candidates' LM values
+    static constexpr int XB_END = XB + xb_below(M) + L * words_of(M); // the root: side 0 only
+    // per level s = 3..M: metrics and ancestors of both children's outputs
+    static constexpr int PM = XB_END;                 // [M-2][2][L] floats
+    static constexpr int ANC = PM + (M - 2) * 2 * L;  // [M-2][2][L] ints
+    // per permutation-domain node (by its depth on the leftmost spine):
+    // kept candidates, their source path and metric
+    static constexpr int SEL = ANC + (M - 2) * 2 * L;  // [kMaxPerm][2L]
+    static constexpr int ORIG = SEL + kMaxPerm * 2 * L; // [kMaxPerm][L]
+    static constexpr int PPM = ORIG + kMaxPerm * L;     // [kMaxPerm][L]
+    static constexpr int SCR = PPM + kMaxPerm * L;      // 2L floats: the candidates' LM values
     static constexpr int PM0 = SCR + 2 * L;            // L: the root's input metrics
     static constexpr int SIDX = PM0 + L;               // L: FHT survivors' index and sign
     static constexpr int PAR = SIDX + L;               // L: SPC parities of the input paths
@@ -132,11 +135,11 @@ struct BigCtx {
     __device__ float *y() const { return f(Ly::Y); }
     __device__ float *a(int s) const { return f(Ly::a_off(s)); } // row l at a(s) + l*2^s
     __device__ uint32_t *xb(int s, int side) const { return w + Ly::xb_off(s, side); }
-    __device__ float *pm(int s, int side) const { return f(Ly::PM + (s * 2 + side) * L); }
-    __device__ int *anc(int s, int side) const { return i(Ly::ANC + (s * 2 + side) * L); }
-    __device__ int *sel(int s) const { return i(Ly::SEL + s * 2 * L); }
-    __device__ int *orig(int s) const { return i(Ly::ORIG + s * L); }
-    __device__ float *ppm(int s) const { return f(Ly::PPM + s * L); }
+    __device__ float *pm(int s, int side) const { return f(Ly::PM + ((s - 3) * 2 + side) * L); }
+    __device__ int *anc(int s, int side) const { return i(Ly::ANC + ((s - 3) * 2 + side) * L); }
+    __device__ int *sel(int v) const { return i(Ly::SEL + v * 2 * L); }
+    __device__ int *orig(int v) const { return i(Ly::ORIG + v * L); }
+    __device__ float *ppm(int v) const { return f(Ly::PPM + v * L); }
     __device__ const uint32_t *map(int k) const { return dmaps + (size_t)k * kMapWords; }
 };
 
@@ -513,15 +516,17 @@ __device__ void big_node(const BigCtx<M, L> &c, const float *pm_in)
     const bool perm = V >= 0 && c.pfht;
     const int l = c.tid / G, lt = c.tid % G;
     float *ach = c.a(S - 1); // children's LLRs: L rows of h
-    int *sel = c.sel(S);
-    int *orig = c.orig(S);
+    constexpr int VP = V >= 0 ? V : 0; // the node's slot among the spine's permutation nodes
+    static_assert(VP < kMaxPerm, "permutation domain deeper than the layout holds");
+    int *sel = c.sel(VP);
+    int *orig = c.orig(VP);
     const float *pmL_in = pm_in;
     if (perm) {
         // LM of the 2L candidates: sum of |f| over the permuted LLRs of path cc mod L
         constexpr int GH = G / 2;
         const int cc = c.tid / GH, ct = c.tid % GH, src = cc % L;
         MapR<S> mp;
-        load_map<S>(c.map(2 * L + 4 * L * (V >= 0 ? V : 0) + cc), mp);
+        load_map<S>(c.map(2 * L + 4 * L * VP + cc), mp);
         float *scr = ach + cc * (h / 2);
         for (int i = ct; i < h / 2; i += GH) {
             const float v0 = fabsf(big_fminsum(in_llr<M, L, S>(c, src, apply_map<S>(mp, i)),
@@ -552,17 +557,17 @@ __device__ void big_node(const BigCtx<M, L> &c, const float *pm_in)
         __syncthreads();
         if (c.tid < L) {
             orig[c.tid] = sel[c.tid] % L;
-            c.ppm(S)[c.tid] = pm_in[sel[c.tid] % L];
+            c.ppm(VP)[c.tid] = pm_in[sel[c.tid] % L];
         }
         __syncthreads();
-        pmL_in = c.ppm(S);
+        pmL_in = c.ppm(VP);
     }
     // f for the left child
     {
         MapR<S> mp;
         int src = l;
         if (perm) {
-            load_map<S>(c.map(2 * L + 4 * L * (V >= 0 ? V : 0) + sel[l]), mp);
+            load_map<S>(c.map(2 * L + 4 * L * VP + sel[l]), mp);
             src = orig[l];
         }
         for (int i = lt; i < h; i += G) {
@@ -579,7 +584,7 @@ __device__ void big_node(const BigCtx<M, L> &c, const float *pm_in)
         MapR<S> mp;
         int src = k;
         if (perm) {
-            load_map<S>(c.map(2 * L + 4 * L * (V >= 0 ? V : 0) + sel[k]), mp);
+            load_map<S>(c.map(2 * L + 4 * L * VP + sel[k]), mp);
             src = orig[k];
         }
         const uint32_t *xl = c.xb(S - 1, 0);
@@ -604,7 +609,7 @@ __device__ void big_node(const BigCtx<M, L> &c, const float *pm_in)
             uint32_t word = 0;
             if (perm) {
                 MapR<S> inv;
-                load_map<S>(c.map(2 * L + 4 * L * (V >= 0 ? V : 0) + 2 * L + sel[a]), inv);
+                load_map<S>(c.map(2 * L + 4 * L * VP + 2 * L + sel[a]), inv);
                 for (int bt = 0; bt < cmin(32, n); bt++) {
                     const uint32_t j = apply_map<S>(inv, (uint32_t)(wd * 32 + bt));
                     const uint32_t bit = j < (uint32_t)h ? (get_bit<S - 1>(xr, ql, j) ^ get_bit<S - 1>(xl, k, j))
@@ -691,6 +696,25 @@ __global__ void __launch_bounds__(kThreads) rm_biglist_kernel(KernelArgs args)
             args.out_pm[f] = misc[0];
         __syncthreads();
     }
+}
+
+// host side: launch (one workgroup per frame) and registry entry
+template <int M, int R, int L>
+hipError_t launch_big(const KernelArgs &args, int blocks, hipStream_t stream)
+{
+    constexpr size_t lds = Lay<M, L>::BYTES;
+    static const hipError_t attr = hipFuncSetAttribute((const void *)&rm_biglist_kernel<M, R, L>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (attr != hipSuccess)
+        return attr;
+    hipLaunchKernelGGL((rm_biglist_kernel<M, R, L>), dim3(blocks), dim3(kThreads), lds, stream, args);
+    return hipGetLastError();
+}
+
+template <int M, int R, int L>
+constexpr KernelEntry big_entry()
+{
+    return KernelEntry{M, R, L, 1, 0, 2 * L + 4 * L * perm_spine(M, R), &launch_big<M, R, L>, Lay<M, L>::BYTES};
 }
 
 } // namespace big

@@ -66,5 +66,6 @@ KernelTable kernels_codes_d();
 KernelTable kernels_codes_e();
 KernelTable kernels_codes_f();
 KernelTable kernels_codes_g(); // lists of 16, 32 and 64 paths
+KernelTable kernels_codes_h(); // lists of 64 paths, N = 512
 
 } // namespace rmdec

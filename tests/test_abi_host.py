@@ -96,7 +96,7 @@ def test_small_cap_rejected():
 
 @pytest.mark.parametrize("m,r,L", [(7, 2, 1), (9, 2, 4), (9, 2, 1), (8, 3, 8), (8, 2, 4), (10, 2, 4), (5, 2, 2),
                                    (6, 3, 8), (5, 1, 4), (4, 3, 1), (9, 3, 4), (9, 4, 8), (8, 4, 2),
-                                   (9, 4, 32), (8, 3, 64), (8, 2, 16), (9, 2, 32), (6, 2, 16)])
+                                   (9, 4, 32), (8, 3, 64), (8, 2, 16), (9, 2, 32), (6, 2, 16), (9, 2, 64)])
 def test_kernels_built_for_configs(m, r, L):
     assert rmd.rm_supported(m, r, L, rmd.RM_PERM_PFHT)
 

@@ -24,8 +24,8 @@ NONE, PFHT, FRESH = rmd.RM_PERM_NONE, rmd.RM_PERM_PFHT, rmd.RM_PERM_FRESH
 THREADS = min(16, os.cpu_count() or 1)
 PM_RTOL = 1e-5
 BUILT = [(8, 2, 16), (8, 2, 32), (8, 2, 64), (8, 3, 16), (8, 3, 32), (8, 3, 64), (8, 4, 16), (8, 4, 32),
-         (8, 4, 64), (9, 2, 16), (9, 2, 32), (9, 3, 16), (9, 3, 32), (9, 4, 16), (9, 4, 32), (7, 2, 16),
-         (7, 3, 16), (6, 2, 16)]
+         (8, 4, 64), (9, 2, 16), (9, 2, 32), (9, 2, 64), (9, 3, 16), (9, 3, 32), (9, 3, 64), (9, 4, 16),
+         (9, 4, 32), (9, 4, 64), (7, 2, 16), (7, 3, 16), (6, 2, 16)]
 
 
 def gpu_decode(m, r, P, L, seed, mode, llr):
@@ -95,8 +95,16 @@ def test_noiseless_large_list():
 
 def test_unbuilt_large_list_reported():
     assert rmd.rm_supported(9, 4, 32, PFHT) == 1
-    assert rmd.rm_supported(9, 2, 64, PFHT) == 0  # 4*L*N bytes of LLRs exceed the LDS budget
+    assert rmd.rm_supported(9, 2, 64, PFHT) == 1
+    assert rmd.rm_supported(10, 2, 64, PFHT) == 0  # 4*L*N bytes of LLRs exceed the LDS of a workgroup
     assert rmd.rm_supported(10, 2, 32, PFHT) == 0
+
+
+def test_table5_rm29_l64_plain_and_permuted():
+    """Table 5's p-FHT-FSCL-64 on RM(2,9): the list takes 157 KB of LDS."""
+    _, llr = synth.frames(9, 2, 16, 1.5, seed=950)
+    check(9, 2, 1, 64, PFHT, llr, seed=3)
+    check(9, 2, 1, 64, NONE, llr, seed=0)
 
 
 def test_large_list_sampled_launch():
