@@ -28,7 +28,7 @@ namespace rmdec {
 namespace big {
 
 constexpr int kThreads = 512;
-constexpr int kMaxPerm = 4; // permutation-domain nodes on the spine (r - 1 for RM(r, m), r <= 5)
+constexpr int kMaxPerm = 3; // permutation-domain nodes on the spine (r - 1 for RM(r, m), r <= 4)
 
 __host__ __device__ constexpr int words_of(int s) { return s >= 5 ? (1 << (s - 5)) : 1; }
 __host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
@@ -51,21 +51,23 @@ struct Lay {
     }
     static constexpr int XB = A_END;
     static constexpr int XB_END = XB + xb_below(M) + L * words_of(M); // the root: side 0 only
+    // (path and candidate indices are below 256 and kept as bytes, so that
+    // two workgroups fit a CU at L*N = 16384)
     // per level s = 3..M: metrics and ancestors of both children's outputs
-    static constexpr int PM = XB_END;                 // [M-2][2][L] floats
-    static constexpr int ANC = PM + (M - 2) * 2 * L;  // [M-2][2][L] ints
+    static constexpr int PM = XB_END;                   // [M-2][2][L] floats
+    static constexpr int ANC = PM + (M - 2) * 2 * L;    // [M-2][2][L] bytes
     // per permutation-domain node (by its depth on the leftmost spine):
     // kept candidates, their source path and metric
-    static constexpr int SEL = ANC + (M - 2) * 2 * L;  // [kMaxPerm][2L]
-    static constexpr int ORIG = SEL + kMaxPerm * 2 * L; // [kMaxPerm][L]
-    static constexpr int PPM = ORIG + kMaxPerm * L;     // [kMaxPerm][L]
-    static constexpr int SCR = PPM + kMaxPerm * L;      // 2L floats: the candidates' LM values
-    static constexpr int PM0 = SCR + 2 * L;            // L: the root's input metrics
-    static constexpr int SIDX = PM0 + L;               // L: FHT survivors' index and sign
-    static constexpr int PAR = SIDX + L;               // L: SPC parities of the input paths
+    static constexpr int SEL = ANC + (M - 2) * 2 * L / 4; // [kMaxPerm][2L] bytes
+    static constexpr int ORIG = SEL + kMaxPerm * 2 * L / 4; // [kMaxPerm][L] bytes
+    static constexpr int PPM = ORIG + kMaxPerm * L / 4;     // [kMaxPerm][L] floats
+    static constexpr int SCR = PPM + kMaxPerm * L;          // 2L floats: the candidates' LM values
+    static constexpr int PM0 = SCR + 2 * L;                 // L floats: the root's input metrics
+    static constexpr int SIDX = PM0 + L;                    // L uint16: FHT survivors' index and sign
+    static constexpr int PAR = SIDX + L / 2;                // L bytes: SPC parities of the input paths
     // SPC list state, two copies: source path, parity, metric, flips (2 words,
     // at an even word offset for 8-byte accesses)
-    static constexpr int SPC = (PAR + L + 1) & ~1;
+    static constexpr int SPC = (PAR + L / 4 + 1) & ~1;
     static constexpr int SPC_ONE = 5 * L;
     static constexpr int BEST = SPC + 2 * SPC_ONE; // the frame's best codeword, N bits
     static constexpr int MISC = BEST + (N / 32 > 0 ? N / 32 : 1);
@@ -136,9 +138,12 @@ struct BigCtx {
     __device__ float *a(int s) const { return f(Ly::a_off(s)); } // row l at a(s) + l*2^s
     __device__ uint32_t *xb(int s, int side) const { return w + Ly::xb_off(s, side); }
     __device__ float *pm(int s, int side) const { return f(Ly::PM + ((s - 3) * 2 + side) * L); }
-    __device__ int *anc(int s, int side) const { return i(Ly::ANC + ((s - 3) * 2 + side) * L); }
-    __device__ int *sel(int v) const { return i(Ly::SEL + v * 2 * L); }
-    __device__ int *orig(int v) const { return i(Ly::ORIG + v * L); }
+    __device__ uint8_t *b(int off) const { return (uint8_t *)(w + off); }
+    __device__ uint8_t *anc(int s, int side) const { return b(Ly::ANC) + ((s - 3) * 2 + side) * L; }
+    __device__ uint8_t *sel(int v) const { return b(Ly::SEL) + v * 2 * L; }
+    __device__ uint8_t *orig(int v) const { return b(Ly::ORIG) + v * L; }
+    __device__ uint16_t *sidx() const { return (uint16_t *)(w + Ly::SIDX); }
+    __device__ uint8_t *par() const { return b(Ly::PAR); }
     __device__ float *ppm(int v) const { return f(Ly::PPM + v * L); }
     __device__ const uint32_t *map(int k) const { return dmaps + (size_t)k * kMapWords; }
 };
@@ -213,7 +218,7 @@ __device__ __forceinline__ void wave_sort(WaveKeys<NK> &k, int lane)
 // of a wave minimum each emit one entry and advance that list.
 template <int M, int L, int K>
 __device__ void select_smallest(const BigCtx<M, L> &c, const float *metric, int mstride, const uint16_t *code,
-                                int cstride, float *out_pm, int *out_src, int *out_code)
+                                int cstride, float *out_pm, uint8_t *out_src, uint16_t *out_code)
 {
     static_assert(L <= kWave, "one lane per list");
     if (c.tid < kWave) {
@@ -230,8 +235,8 @@ __device__ void select_smallest(const BigCtx<M, L> &c, const float *metric, int 
             const int wl = (int)((m >> 16) & 0xFFFFu), wj = (int)(m & 0xFFFFu);
             if (lane == 0) {
                 out_pm[q] = __uint_as_float((uint32_t)(m >> 32));
-                out_src[q] = wl;
-                out_code[q] = (int)code[wl * cstride + wj];
+                out_src[q] = (uint8_t)wl;
+                out_code[q] = code[wl * cstride + wj];
             }
             if (lane == wl) {
                 ptr++;
@@ -324,12 +329,12 @@ __device__ void fhtl_leaf(const BigCtx<M, L> &c, const float *pm_in)
     __syncthreads();
     // merge: the L smallest of the L*K candidates in the order (metric, l, j)
     select_smallest<M, L, K>(c, c.a(S), n, (const uint16_t *)c.a(S - 1), 2 * h, c.pm(S, SIDE), c.anc(S, SIDE),
-                             c.i(Ly::SIDX));
+                             c.sidx());
     // the survivors' codewords: bit j = sign ^ parity(~(i | j))
     uint32_t *xo = c.xb(S, SIDE);
     for (int q = c.tid; q < L * words_of(S); q += kThreads) {
         const int ql = q / words_of(S), wd = q % words_of(S);
-        const uint32_t code = (uint32_t)c.i(Ly::SIDX)[ql];
+        const uint32_t code = (uint32_t)c.sidx()[ql];
         const uint32_t idx = code >> 1, sg = code & 1u;
         uint32_t word = 0;
         for (int bt = 0; bt < cmin(32, n); bt++) {
@@ -376,7 +381,7 @@ __device__ void spcl_leaf(const BigCtx<M, L> &c, const float *pm_in)
         uint32_t p = 0;
         for (int wd = 0; wd < W; wd++)
             p ^= (uint32_t)__popc(hd[c.tid * W + wd]);
-        c.i(Ly::PAR)[c.tid] = (int)(p & 1u);
+        c.par()[c.tid] = (uint8_t)(p & 1u);
     }
     float *ao = c.a(S) + l * n;                          // [TAU+1] |alpha| at o_t
     uint16_t *ord = (uint16_t *)(c.a(S - 1) + l * (n / 2)); // [TAU+1] o_t
@@ -409,7 +414,7 @@ __device__ void spcl_leaf(const BigCtx<M, L> &c, const float *pm_in)
     auto FL = [&](int b) { return (uint64_t *)c.i(Ly::SPC + b * Ly::SPC_ONE + 3 * L); };
     if (c.tid < L) {
         const int q = c.tid;
-        const int p = c.i(Ly::PAR)[q];
+        const int p = c.par()[q];
         SP(0)[q] = q;
         CP(0)[q] = p;
         const float a0 = c.a(S)[q * n];
@@ -478,14 +483,14 @@ __device__ void spcl_leaf(const BigCtx<M, L> &c, const float *pm_in)
         const uint32_t o0 = os[0];
         if ((int)(o0 >> 5) == wd) {
             const uint32_t hd0 = (hd[sp * W + wd] >> (o0 & 31)) & 1u;
-            const uint32_t par = ((uint32_t)c.i(Ly::PAR)[sp] ^ (uint32_t)__popcll(flips) ^ hd0) & 1u;
+            const uint32_t par = ((uint32_t)c.par()[sp] ^ (uint32_t)__popcll(flips) ^ hd0) & 1u;
             word = (word & ~(1u << (o0 & 31))) | (par << (o0 & 31));
         }
         xo[q] = word;
     }
     if (c.tid < L) {
         c.pm(S, SIDE)[c.tid] = CPM(cur)[c.tid];
-        c.anc(S, SIDE)[c.tid] = SP(cur)[c.tid];
+        c.anc(S, SIDE)[c.tid] = (uint8_t)SP(cur)[c.tid];
     }
     __syncthreads();
 }
@@ -518,8 +523,8 @@ __device__ void big_node(const BigCtx<M, L> &c, const float *pm_in)
     float *ach = c.a(S - 1); // children's LLRs: L rows of h
     constexpr int VP = V >= 0 ? V : 0; // the node's slot among the spine's permutation nodes
     static_assert(VP < kMaxPerm, "permutation domain deeper than the layout holds");
-    int *sel = c.sel(VP);
-    int *orig = c.orig(VP);
+    uint8_t *sel = c.sel(VP);
+    uint8_t *orig = c.orig(VP);
     const float *pmL_in = pm_in;
     if (perm) {
         // LM of the 2L candidates: sum of |f| over the permuted LLRs of path cc mod L
@@ -552,11 +557,11 @@ __device__ void big_node(const BigCtx<M, L> &c, const float *pm_in)
                 const float u = lm[o];
                 rank += (u > v || (u == v && o < c.tid)) ? 1 : 0;
             }
-            sel[rank] = c.tid;
+            sel[rank] = (uint8_t)c.tid;
         }
         __syncthreads();
         if (c.tid < L) {
-            orig[c.tid] = sel[c.tid] % L;
+            orig[c.tid] = (uint8_t)(sel[c.tid] % L);
             c.ppm(VP)[c.tid] = pm_in[sel[c.tid] % L];
         }
         __syncthreads();
@@ -629,7 +634,7 @@ __device__ void big_node(const BigCtx<M, L> &c, const float *pm_in)
         if (c.tid < L) {
             const int k = c.anc(S - 1, 1)[c.tid];
             const int a = c.anc(S - 1, 0)[k];
-            c.anc(S, SIDE)[c.tid] = perm ? orig[a] : a;
+            c.anc(S, SIDE)[c.tid] = (uint8_t)(perm ? orig[a] : a);
             c.pm(S, SIDE)[c.tid] = c.pm(S - 1, 1)[c.tid];
         }
         __syncthreads();
