@@ -123,6 +123,21 @@ __device__ __forceinline__ uint64_t group_umin(uint64_t v)
 {
     return ~bfly_umax<G / 2>(~v);
 }
+// smallest 64-bit key of the whole wave (all 64 lanes active), the same in
+// every lane: DPP butterflies within each row of 16 lanes, then the four row
+// minima read into uniform registers (no LDS-routed lane exchange)
+__device__ __forceinline__ uint64_t wave_umin(uint64_t v)
+{
+    const uint64_t r = group_umin<16>(v);
+    auto row = [&](int lane) {
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)r, lane);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(r >> 32), lane);
+        return ((uint64_t)hi << 32) | lo;
+    };
+    const uint64_t a = row(0), b = row(16), c = row(32), d = row(48);
+    const uint64_t ab = a < b ? a : b, cd = c < d ? c : d;
+    return ab < cd ? ab : cd;
+}
 
 template <int M, int L>
 struct BigCtx {
@@ -213,9 +228,11 @@ __device__ __forceinline__ void wave_sort(WaveKeys<NK> &k, int lane)
 // keep the L smallest entries in the order (metric, l, j), as a stable merge
 // of the lists would: out_pm[q], out_src[q] = l and out_code[q] =
 // code[l*cstride + j] for q = 0..L-1 in that order.  A tournament in wave 0:
-// lane l holds the head of list l as the key (metric bits, l, j) (metrics
-// are non-negative, so their bit patterns order as the values do); L rounds
-// of a wave minimum each emit one entry and advance that list.
+// lane l holds the next four entries of list l as keys (metric bits, l, j)
+// (metrics are non-negative, so their bit patterns order as the values do);
+// each of L rounds takes the wave minimum, which lane q keeps for round q,
+// and the winning lane shifts its window, reloading it only when it has
+// used all four.  The outputs are then written by lanes 0..L-1 together.
 template <int M, int L, int K>
 __device__ void select_smallest(const BigCtx<M, L> &c, const float *metric, int mstride, const uint16_t *code,
                                 int cstride, float *out_pm, uint8_t *out_src, uint16_t *out_code)
@@ -228,21 +245,33 @@ __device__ void select_smallest(const BigCtx<M, L> &c, const float *metric, int 
                                              ((uint64_t)lane << 16) | (uint64_t)j
                                        : ~0ull;
         };
-        int ptr = 0;
-        uint64_t head = key_at(0), next = key_at(1); // the next entry is loaded a round ahead
+        uint64_t w0 = key_at(0), w1 = key_at(1), w2 = key_at(2), w3 = key_at(3);
+        int nxt = 4;             // next entry of the list not yet in the window
+        uint64_t mine = ~0ull;   // the winner of round `lane`
         for (int q = 0; q < L; q++) {
-            const uint64_t m = group_umin<kWave>(head);
-            const int wl = (int)((m >> 16) & 0xFFFFu), wj = (int)(m & 0xFFFFu);
-            if (lane == 0) {
-                out_pm[q] = __uint_as_float((uint32_t)(m >> 32));
-                out_src[q] = (uint8_t)wl;
-                out_code[q] = code[wl * cstride + wj];
+            const uint64_t m = wave_umin(w0);
+            mine = lane == q ? m : mine;
+            const bool won = lane == (int)((m >> 16) & 0xFFFFu);
+            w0 = won ? w1 : w0;
+            w1 = won ? w2 : w1;
+            w2 = won ? w3 : w2;
+            w3 = won ? ~0ull : w3;
+            const bool refill = won && w0 == ~0ull && nxt < K;
+            if (__any(refill)) {
+                if (refill) {
+                    w0 = key_at(nxt);
+                    w1 = key_at(nxt + 1);
+                    w2 = key_at(nxt + 2);
+                    w3 = key_at(nxt + 3);
+                    nxt += 4;
+                }
             }
-            if (lane == wl) {
-                ptr++;
-                head = next;
-                next = key_at(ptr + 1);
-            }
+        }
+        if (lane < L) {
+            const int wl = (int)((mine >> 16) & 0xFFFFu), wj = (int)(mine & 0xFFFFu);
+            out_pm[lane] = __uint_as_float((uint32_t)(mine >> 32));
+            out_src[lane] = (uint8_t)wl;
+            out_code[lane] = code[wl * cstride + wj];
         }
     }
     __syncthreads();
