@@ -234,7 +234,7 @@ __device__ __forceinline__ void wave_sort(WaveKeys<NK> &k, int lane)
 // and the winning lane shifts its window, reloading it only when it has
 // used all four.  The outputs are then written by lanes 0..L-1 together.
 template <int M, int L, int K>
-__device__ void select_smallest(const BigCtx<M, L> &c, const float *metric, int mstride, const uint16_t *code,
+__device__ __forceinline__ void select_smallest(const BigCtx<M, L> &c, const float *metric, int mstride, const uint16_t *code,
                                 int cstride, float *out_pm, uint8_t *out_src, uint16_t *out_code)
 {
     static_assert(L <= kWave, "one lane per list");
@@ -281,7 +281,7 @@ __device__ void select_smallest(const BigCtx<M, L> &c, const float *metric, int 
 // FHTL leaf RM(1,S) (Alg. 3, 4)
 // ---------------------------------------------------------------------------
 template <int M, int L, int S, int SIDE>
-__device__ void fhtl_leaf(const BigCtx<M, L> &c, const float *pm_in)
+__device__ __forceinline__ void fhtl_leaf(const BigCtx<M, L> &c, const float *pm_in)
 {
     using Ly = Lay<M, L>;
     constexpr int n = 1 << S, h = n / 2, K = cmin(L, n), G = Ly::G;
@@ -379,7 +379,7 @@ __device__ void fhtl_leaf(const BigCtx<M, L> &c, const float *pm_in)
 // SPCL leaf RM(S-1,S) (Eqs. (2)-(6))
 // ---------------------------------------------------------------------------
 template <int M, int L, int S, int SIDE>
-__device__ void spcl_leaf(const BigCtx<M, L> &c, const float *pm_in)
+__device__ __forceinline__ void spcl_leaf(const BigCtx<M, L> &c, const float *pm_in)
 {
     using Ly = Lay<M, L>;
     constexpr int n = 1 << S, G = Ly::G, W = words_of(S);
@@ -528,11 +528,24 @@ __device__ void spcl_leaf(const BigCtx<M, L> &c, const float *pm_in)
 // internal node RM(R,S) (Alg. 2); V >= 0: depth on the leftmost spine
 // ---------------------------------------------------------------------------
 template <int M, int L, int R, int S, int V, int SIDE>
-__device__ void big_node(const BigCtx<M, L> &c, const float *pm_in);
+__device__ __forceinline__ void big_node(const BigCtx<M, L> &c, const float *pm_in);
+
+// A copy of the context whose thread index the compiler cannot see through:
+// the whole tree is inlined into the kernel, and without this the addresses
+// and indices derived from the thread index would be computed once and held
+// in registers across every node.
+template <int M, int L>
+__device__ __forceinline__ BigCtx<M, L> node_ctx(const BigCtx<M, L> &c)
+{
+    BigCtx<M, L> d = c;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(d.tid) : "v"(c.tid));
+    return d;
+}
 
 template <int M, int L, int R, int S, int V, int SIDE>
-__device__ __forceinline__ void big_child(const BigCtx<M, L> &c, const float *pm_in)
+__device__ __forceinline__ void big_child(const BigCtx<M, L> &c0, const float *pm_in)
 {
+    const BigCtx<M, L> c = node_ctx(c0);
     if constexpr (R == 1)
         fhtl_leaf<M, L, S, SIDE>(c, pm_in);
     else if constexpr (R == S - 1)
@@ -542,7 +555,7 @@ __device__ __forceinline__ void big_child(const BigCtx<M, L> &c, const float *pm
 }
 
 template <int M, int L, int R, int S, int V, int SIDE>
-__device__ void big_node(const BigCtx<M, L> &c, const float *pm_in)
+__device__ __forceinline__ void big_node(const BigCtx<M, L> &c, const float *pm_in)
 {
     using Ly = Lay<M, L>;
     constexpr int n = 1 << S, h = n / 2, G = Ly::G;
@@ -674,7 +687,7 @@ __device__ void big_node(const BigCtx<M, L> &c, const float *pm_in)
 // the kernel: one workgroup per frame (grid-stride), P decoders per frame
 // ---------------------------------------------------------------------------
 template <int M, int R, int L>
-__global__ void __launch_bounds__(kThreads) rm_biglist_kernel(KernelArgs args)
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) rm_biglist_kernel(KernelArgs args)
 {
     using Ly = Lay<M, L>;
     constexpr int N = 1 << M;
