@@ -160,11 +160,23 @@ __device__ __forceinline__ double xor_lanes(double v)
     return __longlong_as_double((long long)xor_lanes<W>((uint64_t)__double_as_longlong(v)));
 }
 
-// The wave's LDS is addressed by byte offset from the start of the dynamic
-// shared segment.
+// The wave's LDS: the dynamic shared segment.  Gathers address it by LDS
+// byte address (an address-space-3 pointer made from the integer, so each
+// read is one ds_read of the computed address with no base added).  These
+// kernels declare no static LDS, so the segment starts at address 0 and the
+// per-wave slices, multiples of 4N bytes from it, keep the alignment that
+// lets map images be formed by XOR.
 extern __shared__ __align__(16) unsigned char rm_smem[];
-__device__ __forceinline__ float lds_f32(uint32_t byte_addr) { return *(const float *)(rm_smem + byte_addr); }
-__device__ __forceinline__ uint32_t lds_u32(uint32_t byte_addr) { return *(const uint32_t *)(rm_smem + byte_addr); }
+typedef __attribute__((address_space(3))) unsigned char lds_byte;
+__device__ __forceinline__ uint32_t lds_addr(unsigned char *p) { return (uint32_t)(size_t)(lds_byte *)p; }
+__device__ __forceinline__ float lds_f32(uint32_t byte_addr)
+{
+    return *(__attribute__((address_space(3))) const float *)(size_t)byte_addr;
+}
+__device__ __forceinline__ uint32_t lds_u32(uint32_t byte_addr)
+{
+    return *(__attribute__((address_space(3))) const uint32_t *)(size_t)byte_addr;
+}
 
 // min(|a|, |b|) for ordinary numbers, one instruction
 __device__ __forceinline__ float min_abs(float a, float b)
@@ -339,8 +351,8 @@ struct Ctx {
     __device__ int lane_of(int path) const { return (gb + path) * S::G + lg; } // same element, other path
     __device__ int lead_of(int path) const { return (gb + path) * S::G; }      // first lane of a path
     __device__ float *y() const { return (float *)(base + S::O_Y); }
-    __device__ uint32_t y_addr() const { return (uint32_t)(base - rm_smem) + S::O_Y; }
-    __device__ uint32_t stage_addr() const { return (uint32_t)(base - rm_smem) + S::O_STAGE; }
+    __device__ uint32_t y_addr() const { return lds_addr(base) + S::O_Y; }
+    __device__ uint32_t stage_addr() const { return lds_addr(base) + S::O_STAGE; }
     __device__ uint32_t *maps_all() const { return (uint32_t *)(base + S::O_MAPS); }
     __device__ uint32_t *maps() const { return maps_all() + ds * S::MAPS_PER_DEC * kMapWords; }
     __device__ float *stage() const { return (float *)(base + S::O_STAGE); }
@@ -1536,13 +1548,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
 // best metrics through LDS, and the wave holding the first minimum in
 // decoder order writes the codeword -- the result of Alg. 5 over all P, with
 // the request's latency divided by about W.
+// The workgroup's exchange area follows its W wave slices in the dynamic
+// segment (kSplitXBytes more than W slices), since static LDS would move the
+// slices off address 0.
+constexpr int kSplitXBytes = 64;
+
 template <int WPE, class... Codes>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) rm_serve_split_kernel(ServeArgs a)
 {
-    __shared__ uint32_t s_tile;
-    __shared__ float s_best[4];
-    __shared__ int s_map[4];
     const int W = (int)(blockDim.x / kWave);
+    unsigned char *xa = rm_smem + (size_t)W * MaxBytes<Codes...>::value;
+    uint32_t &s_tile = *(uint32_t *)xa;
+    float *s_best = (float *)(xa + 16); // [W], W <= 4
+    int *s_map = (int *)(xa + 32);      // [W]
     while (true) {
         if (threadIdx.x == 0)
             s_tile = atomicAdd(a.head, 1u);

@@ -334,7 +334,8 @@ rm_server *rm_server_create(const rm_server_config *cfg)
     for (int g = 0; e == hipSuccess && g < kGroups; g++) {
         int per_cu = 0;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, c.split > 1 ? group(g).split_kernel : group(g).kernel,
-                                                         kWave * bw, (size_t)bw * group(g).lds_bytes_per_wave);
+                                                         kWave * bw,
+                                                         (size_t)bw * group(g).lds_bytes_per_wave + (c.split > 1 ? kSplitXBytes : 0));
         s->grid_max[g] = std::max(1, per_cu * cus);
     }
     s->batches.resize((size_t)c.depth + 1);

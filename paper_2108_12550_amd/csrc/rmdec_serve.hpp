@@ -41,7 +41,7 @@ struct ServeKernel {
     static hipError_t launch_split(const ServeArgs &a, int blocks, int waves, hipStream_t stream)
     {
         hipLaunchKernelGGL((rm_serve_split_kernel<WPE, C<7, 2>, C<8, 2>, C<9, 2>, C<10, 2>, C<8, 3>>), dim3(blocks),
-                           dim3(kWave * waves), (size_t)waves * Slice::value, stream, a);
+                           dim3(kWave * waves), (size_t)waves * Slice::value + kSplitXBytes, stream, a);
         return hipGetLastError();
     }
     static ServeGroup group() { return ServeGroup{L, Slice::value, kernel(), split_kernel(), &launch, &launch_split}; }
