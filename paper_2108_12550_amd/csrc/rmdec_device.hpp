@@ -830,7 +830,7 @@ __device__ __forceinline__ NodeRes<(1 << S), kWave / (L * D)> fhtl(const Ctx<M, 
         x = (walsh_mask<RR, MaskT>(cw >> ilog2(G)) ^ (lbit ? ~(MaskT)0 : (MaskT)0)) & Ly::FULL;
     else
         x = (MaskT)lbit;
-    return {x, opm, e / K};
+    return {x, opm, (int)((uint32_t)e / K)};
 }
 
 // rank of this lane's value among the n values of its group (smaller first,
@@ -910,7 +910,7 @@ __device__ __forceinline__ NodeRes<(1 << S), kWave / (L * D)> spcl(const Ctx<M, 
     wave_sync();
     const int o0 = spci[g * TS];
     const float a0 = spca[g * TS];
-    const uint32_t hd_o0 = (uint32_t)(from_lane((uint64_t)hd, c.lead_of(g) + (o0 % G)) >> (o0 / G)) & 1u;
+    const uint32_t hd_o0 = (uint32_t)(from_lane((uint64_t)hd, c.lead_of(g) + (int)((uint32_t)o0 % G)) >> ((uint32_t)o0 / G)) & 1u;
     if (lg == 0)
         spcp[g] = par | (hd_o0 << 1);
     float cur = pm;
@@ -954,11 +954,11 @@ __device__ __forceinline__ NodeRes<(1 << S), kWave / (L * D)> spcl(const Ctx<M, 
 #pragma unroll
     for (int t = 1; t <= tau; t++) {
         const int pos = spci[src * TS + t];
-        if (((flips >> t) & 1u) && (pos % G) == lg)
-            x ^= (MaskT)1 << (pos / G);
+        if (((flips >> t) & 1u) && (int)((uint32_t)pos % G) == lg)
+            x ^= (MaskT)1 << ((uint32_t)pos / G);
     }
-    if ((so0 % G) == lg)
-        x = (x & ~((MaskT)1 << (so0 / G))) | ((MaskT)fix << (so0 / G));
+    if ((int)((uint32_t)so0 % G) == lg)
+        x = (x & ~((MaskT)1 << ((uint32_t)so0 / G))) | ((MaskT)fix << ((uint32_t)so0 / G));
     wave_sync();
     return {x, cur, src};
 }
@@ -1050,7 +1050,7 @@ __device__ __forceinline__ int perm_select(const Ctx<M, R, L, D> &c, const uint3
     }
     int *slot = c.slot();
     if (c.lane < L * D)
-        c.slot_all()[c.lane] = c.lane % L;
+        c.slot_all()[c.lane] = (int)((uint32_t)c.lane % L);
     wave_sync();
     if (c.lg == 0) {
         if (r0 < L)
@@ -1095,7 +1095,7 @@ __device__ __forceinline__ NodeRes<(1 << MN), kWave / (L * D)> node(const Ctx<M,
                 wave_sync();
                 sel = perm_select<M, R, L, D, MN>(c, c.maps() + mbase * kMapWords,
                                                   [&](int path) { return c.stage_addr() + (uint32_t)((c.gb + path) * n * 4); });
-                const int org = sel % L;
+                const int org = (int)((uint32_t)sel % L);
                 uint32_t pos[RR];
                 map_positions<MN, G, RR>(c.maps() + (mbase + sel) * kMapWords, c.lg,
                                          c.stage_addr() + (uint32_t)((c.gb + org) * n * 4), pos);
@@ -1137,7 +1137,7 @@ __device__ __forceinline__ NodeRes<(1 << MN), kWave / (L * D)> node(const Ctx<M,
                 for (int j = 0; j < RR; j++)
                     y |= (typename Ly::Mask)(lds_u32(pos[j]) & 1u) << j;
                 x = c.lg < Ly::ACT ? y : (typename Ly::Mask)0;
-                anc = csel % L;
+                anc = (int)((uint32_t)csel % L);
                 wave_sync();
             }
         }
@@ -1248,11 +1248,12 @@ __device__ __forceinline__ Ctx<M, R, L, D> frame_ctx(const KernelArgs &args, uns
     Ctx<M, R, L, D> c;
     c.base = slice;
     c.lane = lane;
-    const int gw = lane / G;
-    c.g = gw % L;
-    c.gb = gw - c.g;
-    c.ds = gw / L;
-    c.lg = lane % G;
+    // lane is in [0, 64): unsigned division and remainder are shifts and masks
+    const uint32_t ul = (uint32_t)lane, gw = ul / G;
+    c.g = (int)(gw % L);
+    c.gb = (int)(gw - gw % L);
+    c.ds = (int)(gw / L);
+    c.lg = (int)(ul % G);
     c.pfht = args.pfht;
     return c;
 }
@@ -1309,7 +1310,7 @@ __device__ __forceinline__ FrameBest decode_decoders(const KernelArgs &args, con
             if (pmin < best) {
                 best = pmin;
                 bestmap = (d0 + t) * args.maps_per_dec + from_lane(r.invmap, (t * L + lstar) * G);
-                if (c.lane / G == t * L + lstar) {
+                if ((int)((uint32_t)c.lane / G) == t * L + lstar) {
                     xb[c.lg] = r.xlo;
                     xb[G + c.lg] = r.xhi;
                 }
