@@ -111,32 +111,49 @@ __device__ __forceinline__ float big_fminsum(float a, float b)
 }
 __device__ __forceinline__ float big_g(float a, float b, uint32_t c) { return b + (1.0f - 2.0f * (float)c) * a; }
 
-// largest / smallest 64-bit key over aligned groups of G lanes (DPP and
-// swizzle butterflies)
+// The selection keys are 64-bit patterns whose high word is the bit pattern
+// of a non-negative finite or infinite float (a metric or an |x|): read as
+// doubles they are finite and non-negative, and for such patterns the order
+// of the doubles is the unsigned order of the bits.  So one v_max_f64 /
+// v_min_f64 compares and selects a pair of keys.  kKeyPad, the double +inf,
+// lies above every key; 0 lies at or below every key.
+constexpr uint64_t kKeyPad = 0x7FF0000000000000ull;
+__device__ __forceinline__ double key_d(uint64_t k) { return __longlong_as_double((long long)k); }
+__device__ __forceinline__ uint64_t d_key(double d) { return (uint64_t)__double_as_longlong(d); }
+template <int W>
+__device__ __forceinline__ double bfly_min(double v)
+{
+    if constexpr (W >= 1)
+        return bfly_min<W / 2>(dmin(v, xor64<span_xor<W>()>(v)));
+    else
+        return v;
+}
+
+// largest / smallest key over aligned groups of G lanes (DPP and swizzle
+// butterflies)
 template <int G>
 __device__ __forceinline__ uint64_t group_umax(uint64_t v)
 {
-    return bfly_umax<G / 2>(v);
+    return d_key(bfly_max<G / 2>(key_d(v)));
 }
 template <int G>
 __device__ __forceinline__ uint64_t group_umin(uint64_t v)
 {
-    return ~bfly_umax<G / 2>(~v);
+    return d_key(bfly_min<G / 2>(key_d(v)));
 }
-// smallest 64-bit key of the whole wave (all 64 lanes active), the same in
-// every lane: DPP butterflies within each row of 16 lanes, then the four row
+// smallest key of the whole wave (all 64 lanes active), the same in every
+// lane: DPP butterflies within each row of 16 lanes, then the four row
 // minima read into uniform registers (no LDS-routed lane exchange)
 __device__ __forceinline__ uint64_t wave_umin(uint64_t v)
 {
-    const uint64_t r = group_umin<16>(v);
+    const double r = bfly_min<8>(key_d(v));
     auto row = [&](int lane) {
-        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)r, lane);
-        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(r >> 32), lane);
-        return ((uint64_t)hi << 32) | lo;
+        const uint64_t u = d_key(r);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+        return key_d(((uint64_t)hi << 32) | lo);
     };
-    const uint64_t a = row(0), b = row(16), c = row(32), d = row(48);
-    const uint64_t ab = a < b ? a : b, cd = c < d ? c : d;
-    return ab < cd ? ab : cd;
+    return d_key(dmin(dmin(row(0), row(16)), dmin(row(32), row(48))));
 }
 
 template <int M, int L>
@@ -243,11 +260,11 @@ __device__ __forceinline__ void select_smallest(const BigCtx<M, L> &c, const flo
         auto key_at = [&](int j) {
             return (lane < L && j < K) ? ((uint64_t)__float_as_uint(metric[lane * mstride + j]) << 32) |
                                              ((uint64_t)lane << 16) | (uint64_t)j
-                                       : ~0ull;
+                                       : kKeyPad;
         };
         uint64_t w0 = key_at(0), w1 = key_at(1), w2 = key_at(2), w3 = key_at(3);
         int nxt = 4;             // next entry of the list not yet in the window
-        uint64_t mine = ~0ull;   // the winner of round `lane`
+        uint64_t mine = kKeyPad; // the winner of round `lane`
         for (int q = 0; q < L; q++) {
             const uint64_t m = wave_umin(w0);
             mine = lane == q ? m : mine;
@@ -255,8 +272,8 @@ __device__ __forceinline__ void select_smallest(const BigCtx<M, L> &c, const flo
             w0 = won ? w1 : w0;
             w1 = won ? w2 : w1;
             w2 = won ? w3 : w2;
-            w3 = won ? ~0ull : w3;
-            const bool refill = won && w0 == ~0ull && nxt < K;
+            w3 = won ? kKeyPad : w3;
+            const bool refill = won && w0 == kKeyPad && nxt < K;
             if (__any(refill)) {
                 if (refill) {
                     w0 = key_at(nxt);
@@ -403,7 +420,7 @@ __device__ __forceinline__ void spcl_leaf(const BigCtx<M, L> &c, const float *pm
 #pragma unroll
     for (int e = 0; e < E; e++) {
         const int i = lt + e * G;
-        key[e] = i < n ? (((uint64_t)(__float_as_uint(al[i]) & 0x7FFFFFFFu) << 32) | (uint32_t)i) : ~0ull;
+        key[e] = i < n ? (((uint64_t)(__float_as_uint(al[i]) & 0x7FFFFFFFu) << 32) | (uint32_t)i) : kKeyPad;
     }
     __syncthreads();
     if (c.tid < L) {
@@ -415,7 +432,7 @@ __device__ __forceinline__ void spcl_leaf(const BigCtx<M, L> &c, const float *pm
     float *ao = c.a(S) + l * n;                          // [TAU+1] |alpha| at o_t
     uint16_t *ord = (uint16_t *)(c.a(S - 1) + l * (n / 2)); // [TAU+1] o_t
     for (int t = 0; t <= TAU; t++) {
-        uint64_t b = ~0ull;
+        uint64_t b = kKeyPad;
         int be = -1;
 #pragma unroll
         for (int e = 0; e < E; e++)
@@ -428,7 +445,7 @@ __device__ __forceinline__ void spcl_leaf(const BigCtx<M, L> &c, const float *pm
 #pragma unroll
             for (int e = 0; e < E; e++)
                 if (e == be)
-                    key[e] = ~0ull;
+                    key[e] = kKeyPad;
         }
         if (lt == 0) {
             ao[t] = __uint_as_float((uint32_t)(gb >> 32));
