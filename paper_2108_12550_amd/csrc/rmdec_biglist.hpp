@@ -349,22 +349,17 @@ __device__ __forceinline__ void fhtl_leaf(const BigCtx<M, L> &c, const float *pm
     // K passes: the group's largest remaining key
     float *metric = F;                                   // [K] per path, in the path's own row
     uint16_t *cidx = (uint16_t *)(c.a(S - 1) + l * h); // [K] index << 1 | sign
+    // (keys are distinct and above 0, the padding, so exactly one lane holds
+    // the group maximum and drops it by equality)
     for (int j = 0; j < K; j++) {
-        uint64_t b = 0;
-        int be = -1;
+        double b = 0.0;
 #pragma unroll
         for (int e = 0; e < E; e++)
-            if (key[e] > b) {
-                b = key[e];
-                be = e;
-            }
-        const uint64_t gb = group_umax<G>(b);
-        if (be >= 0 && gb == b) {
+            b = dmax(b, key_d(key[e]));
+        const uint64_t gb = d_key(bfly_max<G / 2>(b));
 #pragma unroll
-            for (int e = 0; e < E; e++)
-                if (e == be)
-                    key[e] = 0;
-        }
+        for (int e = 0; e < E; e++)
+            key[e] = key[e] == gb ? 0ull : key[e];
         if (lt == 0) {
             const float absf = __uint_as_float((uint32_t)(gb >> 32));
             const uint32_t idx = 0xFFFFu - (uint32_t)((gb >> 1) & 0xFFFFu);
