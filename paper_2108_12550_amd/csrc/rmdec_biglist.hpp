@@ -475,21 +475,45 @@ __device__ __forceinline__ void spcl_leaf(const BigCtx<M, L> &c, const float *pm
         int cur = 0;
         for (int t = 1; t <= TAU; t++) {
             WaveKeys<NK> key;
+            if (NK > kWave && t > 1) {
+                // L = 64: after the first round the list is in metric order,
+                // so the keep candidates (lane q: entry q, position 2q) are
+                // already sorted.  Sort the L flips alone, then keep the L
+                // smallest of the two sorted lists: the minimum of keep q and
+                // flip L-1-q is a bitonic sequence holding them, which the
+                // half-cleaners sort.
+                const int q = lane;
+                const int sp = SP(cur)[q];
+                const float *aos = c.a(S) + sp * n;
+                const float cpm = CPM(cur)[q];
+                const float fv = (cpm + aos[t]) + (1.0f - 2.0f * (float)CP(cur)[q]) * aos[0];
+                WaveKeys<kWave> fk, z;
+                fk[0] = ((uint64_t)__float_as_uint(fv) << 32) | (uint32_t)(2 * q + 1);
+                wave_sort<kWave>(fk, lane);
+                const uint64_t kk = ((uint64_t)__float_as_uint(cpm) << 32) | (uint32_t)(2 * q);
+                z[0] = d_key(dmin(key_d(kk), xor64<kWave - 1>(key_d(fk[0]))));
+                wave_sort_run<kWave, kWave, kWave / 2>(z, lane);
+                key[0] = z[0];
 #pragma unroll
-            for (int r = 0; r < NR; r++) {
-                const int e = lane + kWave * r;
-                if (e < 2 * L) {
-                    const int q = e >> 1, fl = e & 1;
-                    const int sp = SP(cur)[q];
-                    const float *aos = c.a(S) + sp * n;
-                    const float v =
-                        fl ? (CPM(cur)[q] + aos[t]) + (1.0f - 2.0f * (float)CP(cur)[q]) * aos[0] : CPM(cur)[q];
-                    key[r] = ((uint64_t)__float_as_uint(v) << 32) | (uint32_t)e;
-                } else {
-                    key[r] = ~0ull;
+                for (int r = 1; r < NR; r++)
+                    key[r] = kKeyPad; // ranks past L: not used
+            } else {
+#pragma unroll
+                for (int r = 0; r < NR; r++) {
+                    const int e = lane + kWave * r;
+                    if (e < 2 * L) {
+                        const int q = e >> 1, fl = e & 1;
+                        const int sp = SP(cur)[q];
+                        const float *aos = c.a(S) + sp * n;
+                        const float v =
+                            fl ? (CPM(cur)[q] + aos[t]) + (1.0f - 2.0f * (float)CP(cur)[q]) * aos[0] : CPM(cur)[q];
+                        key[r] = ((uint64_t)__float_as_uint(v) << 32) | (uint32_t)e;
+                    } else {
+                        key[r] = ~0ull;
+                    }
                 }
+                wave_sort<NK>(key, lane);
             }
-            wave_sort<NK>(key, lane);
 #pragma unroll
             for (int r = 0; r < NR; r++) {
                 const int rank = lane + kWave * r;
@@ -675,13 +699,15 @@ __device__ __forceinline__ void big_node(const BigCtx<M, L> &c, const float *pm_
                                                          : get_bit<S - 1>(xr, ql, j - h);
                     word |= bit << bt;
                 }
+            } else if constexpr (S - 1 >= 5) {
+                // whole words: the first half x_R ^ x_L, the second x_R
+                constexpr int WC = words_of(S - 1);
+                word = wd < WC ? (xr[ql * WC + wd] ^ xl[k * WC + wd]) : xr[ql * WC + wd - WC];
             } else {
-                for (int bt = 0; bt < cmin(32, n); bt++) {
-                    const uint32_t j = (uint32_t)(wd * 32 + bt);
-                    const uint32_t bit = j < (uint32_t)h ? (get_bit<S - 1>(xr, ql, j) ^ get_bit<S - 1>(xl, k, j))
-                                                         : get_bit<S - 1>(xr, ql, j - h);
-                    word |= bit << bt;
-                }
+                // both children's h bits in one word each
+                constexpr uint32_t HM = (1u << h) - 1u;
+                const uint32_t wr = xr[ql] & HM;
+                word = (wr ^ (xl[k] & HM)) | (wr << h);
             }
             xo[q] = word;
         }
