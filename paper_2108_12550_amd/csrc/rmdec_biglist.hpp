@@ -141,19 +141,31 @@ __device__ __forceinline__ uint64_t group_umin(uint64_t v)
 {
     return d_key(bfly_min<G / 2>(key_d(v)));
 }
+// row broadcast (DPP): rows whose bit is set in RM take lane CTRL's value
+// from the row below (row_bcast:15 = 0x142, row_bcast:31 = 0x143); the
+// other rows keep their own
+template <int CTRL, int RM>
+__device__ __forceinline__ double row_bcast(double v)
+{
+    const uint64_t u = d_key(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)u, (int)(uint32_t)u, CTRL, RM, 0xF, false);
+    const uint32_t hi =
+        (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(u >> 32), (int)(uint32_t)(u >> 32), CTRL, RM, 0xF, false);
+    return key_d(((uint64_t)hi << 32) | lo);
+}
 // smallest key of the whole wave (all 64 lanes active), the same in every
-// lane: DPP butterflies within each row of 16 lanes, then the four row
-// minima read into uniform registers (no LDS-routed lane exchange)
+// lane: DPP butterflies within each row of 16 lanes, then two row
+// broadcasts that leave the minimum of all four rows in lane 63, read into
+// uniform registers (no LDS-routed lane exchange)
 __device__ __forceinline__ uint64_t wave_umin(uint64_t v)
 {
-    const double r = bfly_min<8>(key_d(v));
-    auto row = [&](int lane) {
-        const uint64_t u = d_key(r);
-        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
-        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
-        return key_d(((uint64_t)hi << 32) | lo);
-    };
-    return d_key(dmin(dmin(row(0), row(16)), dmin(row(32), row(48))));
+    double r = bfly_min<8>(key_d(v));
+    r = dmin(r, row_bcast<0x142, 0xA>(r)); // rows 1, 3: with rows 0, 2
+    r = dmin(r, row_bcast<0x143, 0xC>(r)); // rows 2, 3: with row 1's result
+    const uint64_t u = d_key(r);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), 63);
+    return ((uint64_t)hi << 32) | lo;
 }
 
 template <int M, int L>
