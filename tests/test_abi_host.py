@@ -3,7 +3,9 @@
 * the library loads and exports every function include/rmdec.h declares;
 * the permutation draw of the library equals the oracle's own, independent
   implementation of the same published sampler (SplitMix64 + rejection);
-* argument validation and the list of built kernels.
+* argument validation and the list of built kernels;
+* two facts the kernels rely on: no kernel declares static LDS, and the
+  large-list selection keys order as doubles the way they order as bits.
 """
 import os
 import re
@@ -177,3 +179,41 @@ def test_server_create_without_device_fails_cleanly():
         pytest.skip("a GPU is present")
     assert rmd.rm_server_create(rmd.rm_server_config(1 << 20, 64, 2, 0, 0)) == 0
     assert "HIP" in rmd.rm_last_error()
+
+
+def test_no_kernel_declares_static_lds():
+    # The gathers address LDS by absolute address and form element addresses
+    # by XOR, which needs the dynamic segment to start at address 0: no
+    # kernel may declare a static __shared__ variable.
+    csrc = os.path.join(ROOT, "paper_2108_12550_amd", "csrc")
+    found = []
+    for name in sorted(os.listdir(csrc)):
+        if not name.endswith((".hip", ".hpp")):
+            continue
+        src = re.sub(r"//[^\n]*", "", open(os.path.join(csrc, name)).read())
+        for line in src.splitlines():
+            if "__shared__" in line and "extern __shared__" not in line:
+                found.append(f"{name}: {line.strip()}")
+    assert not found, found
+
+
+def test_selection_keys_order_as_doubles():
+    # The large-list kernels compare 64-bit keys (high word: the bits of a
+    # non-negative float, finite or +inf; low word: any index code) with
+    # v_min_f64 / v_max_f64.  For such patterns the order of the doubles is
+    # the unsigned order of the bits, and the double +inf (the padding key)
+    # lies above every key.
+    rng = np.random.default_rng(7)
+    n = 200_000
+    hi = rng.integers(0, 0x7F800001, size=n, dtype=np.uint64)
+    hi[: n // 10] = rng.integers(0, 4, size=n // 10, dtype=np.uint64)  # near-equal high words
+    hi[n // 10 : n // 5] = 0x7F800000  # +inf metrics
+    lo = rng.integers(0, 1 << 32, size=n, dtype=np.uint64)
+    keys = (hi << np.uint64(32)) | lo
+    a, b = keys, rng.permutation(keys)
+    da, db = a.view(np.float64), b.view(np.float64)
+    assert np.all(np.isfinite(da)) and np.all(da >= 0)
+    assert np.array_equal(a < b, da < db)
+    assert np.array_equal(a == b, da == db)
+    pad = np.array([0x7FF0000000000000], dtype=np.uint64).view(np.float64)[0]
+    assert np.all(da < pad) and np.all(keys < np.uint64(0x7FF0000000000000))
