@@ -95,6 +95,20 @@ __device__ __forceinline__ void load_map(const uint32_t *mp, MapR<S> &m)
 }
 
 template <int S>
+__device__ __forceinline__ void identity_map(MapR<S> &m)
+{
+#pragma unroll
+    for (int k = 0; k < S; k++)
+        m.col[k] = 1u << k;
+    m.b = 0;
+}
+
+// Loops over i = t0 + STEP*x (x < NIT, a power of two, t0 < STEP) that need
+// p(i) visit x in Gray-code order, x_t = t ^ (t >> 1): consecutive x differ
+// in bit ctz(t), so p(i) changes by one column, p_t = p_{t-1} ^ col[log2
+// STEP + ctz(t)], one XOR per index instead of one per set bit.  The loops
+// are unrolled, so the column index is a constant.
+template <int S>
 __device__ __forceinline__ uint32_t apply_map(const MapR<S> &m, uint32_t i)
 {
     uint32_t p = m.b;
@@ -623,12 +637,20 @@ __device__ __forceinline__ void big_node(const BigCtx<M, L> &c, const float *pm_
         MapR<S> mp;
         load_map<S>(c.map(2 * L + 4 * L * VP + cc), mp);
         float *scr = ach + cc * (h / 2);
-        for (int i = ct; i < h / 2; i += GH) {
-            const float v0 = fabsf(big_fminsum(in_llr<M, L, S>(c, src, apply_map<S>(mp, i)),
-                                               in_llr<M, L, S>(c, src, apply_map<S>(mp, i + h))));
-            const float v1 = fabsf(big_fminsum(in_llr<M, L, S>(c, src, apply_map<S>(mp, i + h / 2)),
-                                               in_llr<M, L, S>(c, src, apply_map<S>(mp, i + h / 2 + h))));
-            scr[i] = v0 + v1;
+        constexpr int NIT = (h / 2 + GH - 1) / GH, LS = ilog2(GH);
+        uint32_t p = apply_map<S>(mp, (uint32_t)ct); // p(i), Gray-code walk
+#pragma unroll
+        for (int it = 0; it < NIT; it++) {
+            if (it > 0)
+                p ^= mp.col[LS + __builtin_ctz(it)];
+            const int i = ct + GH * (it ^ (it >> 1));
+            if (i < h / 2) {
+                const uint32_t ph = p ^ mp.col[S - 1], pq = p ^ mp.col[S - 2]; // p(i + h), p(i + h/2)
+                const float v0 = fabsf(big_fminsum(in_llr<M, L, S>(c, src, p), in_llr<M, L, S>(c, src, ph)));
+                const float v1 = fabsf(
+                    big_fminsum(in_llr<M, L, S>(c, src, pq), in_llr<M, L, S>(c, src, pq ^ mp.col[S - 1])));
+                scr[i] = v0 + v1;
+            }
         }
         wave_sync(); // a candidate's GH threads are lanes of one wave
         for (int wdt = h / 4; wdt >= 1; wdt /= 2) {
@@ -658,35 +680,61 @@ __device__ __forceinline__ void big_node(const BigCtx<M, L> &c, const float *pm_
         pmL_in = c.ppm(VP);
     }
     // f for the left child
-    {
+    if constexpr (V >= 0) {
+        // the permutation domain: the node's map, or the identity without
+        // permutations, walked in Gray-code order
         MapR<S> mp;
         int src = l;
         if (perm) {
             load_map<S>(c.map(2 * L + 4 * L * VP + sel[l]), mp);
             src = orig[l];
+        } else {
+            identity_map<S>(mp);
         }
-        for (int i = lt; i < h; i += G) {
-            const uint32_t i0 = perm ? apply_map<S>(mp, i) : (uint32_t)i;
-            const uint32_t i1 = perm ? apply_map<S>(mp, i + h) : (uint32_t)(i + h);
-            ach[l * h + i] = big_fminsum(in_llr<M, L, S>(c, src, i0), in_llr<M, L, S>(c, src, i1));
+        constexpr int NIT = (h + G - 1) / G, LG = ilog2(G);
+        uint32_t p = apply_map<S>(mp, (uint32_t)lt);
+#pragma unroll
+        for (int it = 0; it < NIT; it++) {
+            if (it > 0)
+                p ^= mp.col[LG + __builtin_ctz(it)];
+            const int i = lt + G * (it ^ (it >> 1));
+            if (i < h)
+                ach[l * h + i] = big_fminsum(in_llr<M, L, S>(c, src, p), in_llr<M, L, S>(c, src, p ^ mp.col[S - 1]));
         }
+    } else {
+        for (int i = lt; i < h; i += G)
+            ach[l * h + i] = big_fminsum(in_llr<M, L, S>(c, l, (uint32_t)i), in_llr<M, L, S>(c, l, (uint32_t)(i + h)));
     }
     __syncthreads();
     big_child<M, L, R - 1, S - 1, (V >= 0 ? V + 1 : -1), 0>(c, pmL_in);
     // g for the right child, from the surviving ancestor's LLRs
     {
         const int k = c.anc(S - 1, 0)[l];
-        MapR<S> mp;
-        int src = k;
-        if (perm) {
-            load_map<S>(c.map(2 * L + 4 * L * VP + sel[k]), mp);
-            src = orig[k];
-        }
         const uint32_t *xl = c.xb(S - 1, 0);
-        for (int i = lt; i < h; i += G) {
-            const uint32_t i0 = perm ? apply_map<S>(mp, i) : (uint32_t)i;
-            const uint32_t i1 = perm ? apply_map<S>(mp, i + h) : (uint32_t)(i + h);
-            ach[l * h + i] = big_g(in_llr<M, L, S>(c, src, i0), in_llr<M, L, S>(c, src, i1), get_bit<S - 1>(xl, l, i));
+        if constexpr (V >= 0) {
+            MapR<S> mp;
+            int src = k;
+            if (perm) {
+                load_map<S>(c.map(2 * L + 4 * L * VP + sel[k]), mp);
+                src = orig[k];
+            } else {
+                identity_map<S>(mp);
+            }
+            constexpr int NIT = (h + G - 1) / G, LG = ilog2(G);
+            uint32_t p = apply_map<S>(mp, (uint32_t)lt);
+#pragma unroll
+            for (int it = 0; it < NIT; it++) {
+                if (it > 0)
+                    p ^= mp.col[LG + __builtin_ctz(it)];
+                const int i = lt + G * (it ^ (it >> 1));
+                if (i < h)
+                    ach[l * h + i] = big_g(in_llr<M, L, S>(c, src, p), in_llr<M, L, S>(c, src, p ^ mp.col[S - 1]),
+                                           get_bit<S - 1>(xl, l, (uint32_t)i));
+            }
+        } else {
+            for (int i = lt; i < h; i += G)
+                ach[l * h + i] = big_g(in_llr<M, L, S>(c, k, (uint32_t)i), in_llr<M, L, S>(c, k, (uint32_t)(i + h)),
+                                       get_bit<S - 1>(xl, l, (uint32_t)i));
         }
     }
     __syncthreads();
@@ -705,11 +753,15 @@ __device__ __forceinline__ void big_node(const BigCtx<M, L> &c, const float *pm_
             if (perm) {
                 MapR<S> inv;
                 load_map<S>(c.map(2 * L + 4 * L * VP + 2 * L + sel[a]), inv);
-                for (int bt = 0; bt < cmin(32, n); bt++) {
-                    const uint32_t j = apply_map<S>(inv, (uint32_t)(wd * 32 + bt));
+                constexpr int NB = cmin(32, n);
+                uint32_t j = apply_map<S>(inv, (uint32_t)(wd * 32)); // Gray-code walk over the word's bits
+#pragma unroll
+                for (int it = 0; it < NB; it++) {
+                    if (it > 0)
+                        j ^= inv.col[__builtin_ctz(it)];
                     const uint32_t bit = j < (uint32_t)h ? (get_bit<S - 1>(xr, ql, j) ^ get_bit<S - 1>(xl, k, j))
                                                          : get_bit<S - 1>(xr, ql, j - h);
-                    word |= bit << bt;
+                    word |= bit << (it ^ (it >> 1));
                 }
             } else if constexpr (S - 1 >= 5) {
                 // whole words: the first half x_R ^ x_L, the second x_R
