@@ -167,19 +167,44 @@ __device__ __forceinline__ double row_bcast(double v)
         (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(u >> 32), (int)(uint32_t)(u >> 32), CTRL, RM, 0xF, false);
     return key_d(((uint64_t)hi << 32) | lo);
 }
-// smallest key of the whole wave (all 64 lanes active), the same in every
-// lane: DPP butterflies within each row of 16 lanes, then two row
-// broadcasts that leave the minimum of all four rows in lane 63, read into
-// uniform registers (no LDS-routed lane exchange)
-__device__ __forceinline__ uint64_t wave_umin(uint64_t v)
+// the two smallest of two disjoint sets given by their two smallest
+// (x1 <= x2, y1 <= y2)
+__device__ __forceinline__ void merge_two(double &x1, double &x2, double y1, double y2)
 {
-    double r = bfly_min<8>(key_d(v));
-    r = dmin(r, row_bcast<0x142, 0xA>(r)); // rows 1, 3: with rows 0, 2
-    r = dmin(r, row_bcast<0x143, 0xC>(r)); // rows 2, 3: with row 1's result
-    const uint64_t u = d_key(r);
+    const double s1 = dmin(x1, y1);
+    x2 = dmin(dmax(x1, y1), dmin(x2, y2));
+    x1 = s1;
+}
+template <int W>
+__device__ __forceinline__ void bfly_min2(double &x1, double &x2)
+{
+    if constexpr (W >= 1) {
+        const double y1 = xor64<span_xor<W>()>(x1), y2 = xor64<span_xor<W>()>(x2);
+        merge_two(x1, x2, y1, y2);
+        bfly_min2<W / 2>(x1, x2);
+    }
+}
+__device__ __forceinline__ uint64_t lane63(double v)
+{
+    const uint64_t u = d_key(v);
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, 63);
     const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), 63);
     return ((uint64_t)hi << 32) | lo;
+}
+// The two smallest keys of the whole wave (all 64 lanes active), each lane
+// offering its two smallest (v1 <= v2): butterflies within each row of 16
+// lanes (the strides 8, 7, 2, 1 pair disjoint sets at every level), then the
+// two row broadcasts; lane 63 ends with all four rows (the rows that keep
+// their own value in a broadcast merge with themselves, but lane 63 never
+// reads them).
+__device__ __forceinline__ void wave_umin2(uint64_t v1, uint64_t v2, uint64_t &m1, uint64_t &m2)
+{
+    double x1 = key_d(v1), x2 = key_d(v2);
+    bfly_min2<8>(x1, x2);
+    merge_two(x1, x2, row_bcast<0x142, 0xA>(x1), row_bcast<0x142, 0xA>(x2));
+    merge_two(x1, x2, row_bcast<0x143, 0xC>(x1), row_bcast<0x143, 0xC>(x2));
+    m1 = lane63(x1);
+    m2 = lane63(x2);
 }
 
 template <int M, int L>
@@ -273,9 +298,11 @@ __device__ __forceinline__ void wave_sort(WaveKeys<NK> &k, int lane)
 // code[l*cstride + j] for q = 0..L-1 in that order.  A tournament in wave 0:
 // lane l holds the next four entries of list l as keys (metric bits, l, j)
 // (metrics are non-negative, so their bit patterns order as the values do);
-// each of L rounds takes the wave minimum, which lane q keeps for round q,
-// and the winning lane shifts its window, reloading it only when it has
-// used all four.  The outputs are then written by lanes 0..L-1 together.
+// each of L/2 rounds takes the two smallest keys of the wave (from every
+// lane's two smallest remaining entries), which lanes 2r and 2r+1 keep for
+// round r, and the winning lanes shift their windows, reloading once fewer
+// than two entries are left in a window but not in the list.  The outputs
+// are then written by lanes 0..L-1 together.
 template <int M, int L, int K>
 __device__ __forceinline__ void select_smallest(const BigCtx<M, L> &c, const float *metric, int mstride, const uint16_t *code,
                                 int cstride, float *out_pm, uint8_t *out_src, uint16_t *out_code)
@@ -291,22 +318,38 @@ __device__ __forceinline__ void select_smallest(const BigCtx<M, L> &c, const flo
         uint64_t w0 = key_at(0), w1 = key_at(1), w2 = key_at(2), w3 = key_at(3);
         int nxt = 4;             // next entry of the list not yet in the window
         uint64_t mine = kKeyPad; // the winner of round `lane`
-        for (int q = 0; q < L; q++) {
-            const uint64_t m = wave_umin(w0);
-            mine = lane == q ? m : mine;
-            const bool won = lane == (int)((m >> 16) & 0xFFFFu);
-            w0 = won ? w1 : w0;
-            w1 = won ? w2 : w1;
-            w2 = won ? w3 : w2;
-            w3 = won ? kKeyPad : w3;
-            const bool refill = won && w0 == kKeyPad && nxt < K;
+        static_assert(L % 2 == 0, "two winners per round");
+        for (int q = 0; q < L; q += 2) {
+            uint64_t m1, m2;
+            wave_umin2(w0, w1, m1, m2);
+            mine = lane == q ? m1 : (lane == q + 1 ? m2 : mine);
+            const int l1 = (int)((m1 >> 16) & 0xFFFFu), l2 = (int)((m2 >> 16) & 0xFFFFu);
+            const bool p1 = lane == l1 || lane == l2; // pops one entry
+            const bool p2 = lane == l1 && lane == l2; // pops two
+            const uint64_t n0 = p2 ? w2 : (p1 ? w1 : w0);
+            const uint64_t n1 = p2 ? w3 : (p1 ? w2 : w1);
+            const uint64_t n2 = p2 ? kKeyPad : (p1 ? w3 : w2);
+            w3 = p1 ? kKeyPad : w3;
+            w0 = n0;
+            w1 = n1;
+            w2 = n2;
+            // padding sits only at the end of a window, so w1 is the padding
+            // exactly when fewer than two entries are left in it
+            const bool refill = p1 && w1 == kKeyPad && nxt < K;
             if (__any(refill)) {
                 if (refill) {
-                    w0 = key_at(nxt);
-                    w1 = key_at(nxt + 1);
-                    w2 = key_at(nxt + 2);
-                    w3 = key_at(nxt + 3);
-                    nxt += 4;
+                    if (w0 == kKeyPad) {
+                        w0 = key_at(nxt);
+                        w1 = key_at(nxt + 1);
+                        w2 = key_at(nxt + 2);
+                        w3 = key_at(nxt + 3);
+                        nxt += 4;
+                    } else {
+                        w1 = key_at(nxt);
+                        w2 = key_at(nxt + 1);
+                        w3 = key_at(nxt + 2);
+                        nxt += 3;
+                    }
                 }
             }
         }
