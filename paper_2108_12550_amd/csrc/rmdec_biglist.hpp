@@ -495,22 +495,17 @@ __device__ __forceinline__ void spcl_leaf(const BigCtx<M, L> &c, const float *pm
     }
     float *ao = c.a(S) + l * n;                          // [TAU+1] |alpha| at o_t
     uint16_t *ord = (uint16_t *)(c.a(S - 1) + l * (n / 2)); // [TAU+1] o_t
+    // (keys are distinct and below the padding, so exactly one lane holds
+    // the group minimum and drops it by equality)
     for (int t = 0; t <= TAU; t++) {
-        uint64_t b = kKeyPad;
-        int be = -1;
+        double b = key_d(kKeyPad);
 #pragma unroll
         for (int e = 0; e < E; e++)
-            if (key[e] < b) {
-                b = key[e];
-                be = e;
-            }
-        const uint64_t gb = group_umin<G>(b);
-        if (be >= 0 && gb == b) {
+            b = dmin(b, key_d(key[e]));
+        const uint64_t gb = d_key(bfly_min<G / 2>(b));
 #pragma unroll
-            for (int e = 0; e < E; e++)
-                if (e == be)
-                    key[e] = kKeyPad;
-        }
+        for (int e = 0; e < E; e++)
+            key[e] = key[e] == gb ? kKeyPad : key[e];
         if (lt == 0) {
             ao[t] = __uint_as_float((uint32_t)(gb >> 32));
             ord[t] = (uint16_t)(gb & 0xFFFFu);
