@@ -11,7 +11,15 @@ RM(2,7) P=8, RM(2,8) P=16, RM(2,9) P=20 and RM(2,10) P=32, all L = 4, with
 262,144 frames each (1,048,576 per step), Eb/N0 uniform in [2, 4] dB per
 frame; launch choices come from the library's autotuner.
 
-Prints one JSON line.  Diagnostics go to stderr.
+With ``--workload configs``: the other configurations of the evaluation,
+one JSON line each (decode rate, FER per Eb/N0 point, and the ALU roofline
+where the paper gives an operation count): RM(2,7) with one plain FHT-FSC
+decoder (10,000 frames at 3.0 dB), RM(2,9) with 512 permuted decoders of
+list size 1 and RM(3,8) with 8 permuted decoders of list size 8 (131,072
+frames per point, 2.0 to 4.5 dB).
+
+Prints one JSON line (one per configuration with ``--workload configs``).
+Diagnostics go to stderr.
 """
 from __future__ import annotations
 
@@ -113,7 +121,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
-    ap.add_argument("--workload", choices=("rm29", "mixed", "serve", "biglist"), default="rm29")
+    ap.add_argument("--workload", choices=("rm29", "mixed", "serve", "biglist", "configs"), default="rm29")
     ap.add_argument("--serve-ms", type=float, default=100.0, help="arrival window per rate of the serving trace")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving section of the rm29 workload")
     ap.add_argument("--fresh", action="store_true",
@@ -131,6 +139,8 @@ def main():
         return run_serve(args)
     if args.workload == "biglist":
         return run_biglist(args)
+    if args.workload == "configs":
+        return run_configs(args)
 
     import torch
     import paper_2108_12550_amd as rmd
@@ -506,6 +516,70 @@ def run_biglist(args):
                                   "(Table 5, p-FHT-FSCL-L), BPSK/AWGN Eb/N0 3.0 dB", "frames_per_step": n},
            "fer": {"3.0": fer}, "roofline": roof, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
+
+
+# (name, m, r, P, L, permutation mode, frames per point, Eb/N0 points,
+#  operations per frame or None, where they come from)
+CONFIGS = [
+    ("RM(7,2) N=128 K=29 (paper's RM(2,7)), one plain FHT-FSC decoder (P=1, L=1, identity permutation)",
+     7, 2, 1, 1, "none", 10000, [3.0], None, "the paper gives no operation count for this decoder"),
+    ("RM(9,2) N=512 K=46 (paper's RM(2,9)), P=512 permuted decoders, L=1",
+     9, 2, 512, 1, "pfht", 131072, [2.0, 2.5, 3.0, 3.5, 4.0, 4.5], 5.1e5 / 100 * 512,
+     "Table 5's p-FHT-FSCL-1-100 on RM(2,9), 5.1e5 per frame, scaled to 512 decoders"),
+    ("RM(8,3) N=256 K=93 (paper's RM(3,8)), P=8 permuted decoders, L=8",
+     8, 3, 8, 8, "pfht", 131072, [2.0, 2.5, 3.0, 3.5, 4.0, 4.5], None,
+     "the paper gives no operation count for p-FHT-FSCL-8-8"),
+]
+
+
+def run_configs(args):
+    import torch
+    import paper_2108_12550_amd as rmd
+    import synth
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream(device=dev)
+    reps = max(1, min(args.steps, 3))
+    for name, m, r, P, L, mode, n, points, ops, ops_src in CONFIGS:
+        perm = rmd.RM_PERM_NONE if mode == "none" else rmd.RM_PERM_PFHT
+        dec = rmd.Decoder(m, r, P, L, seed=SEED, perm_mode=perm)
+        N = 1 << m
+        bits = torch.empty((n, N // 8), dtype=torch.uint8, device=dev)
+        pm = torch.empty((n,), dtype=torch.float32, device=dev)
+        total_ms, fers = 0.0, {}
+        for k, e in enumerate(points):
+            x, llr = synth.frames(m, r, n, e, seed=SEED + k)
+            t = torch.from_numpy(llr).to(dev)
+            for _ in range(max(1, args.warmup)):
+                dec.decode(t, out_bits=bits, out_metric=pm, stream=stream)
+            torch.cuda.synchronize()
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            for _ in range(reps):
+                dec.decode(t, out_bits=bits, out_metric=pm, stream=stream)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            total_ms += ev0.elapsed_time(ev1) / reps
+            xb = synth.unpack_bits(bits.cpu().numpy(), N)
+            fers[str(e)] = fer_ci(int(np.any(xb != x, axis=1).sum()), n)
+            log(f"{name.split(',')[0]}: {e} dB done")
+        ms = total_ms / len(points)
+        fps = n / (ms / 1e3)
+        roof = None
+        if ops is not None:
+            achieved = ops * fps / 1e12
+            roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(ALU_PEAK_TOPS, 4), "unit": "TFLOP/s",
+                    "frac": round(achieved / ALU_PEAK_TOPS, 5), "traffic": None, "ops_per_frame": ops,
+                    "ops_source": ops_src, "avg_launch_ms": round(ms, 4)}
+        out = {"metric": "frames/s", "value": round(fps, 1), "unit": "frames/s", "n_gpus": 1, "steps": reps,
+               "warmup": max(1, args.warmup), "ms_per_step": round(ms, 4), "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+               "config": {"workload": name + ", BPSK/AWGN", "frames_per_point": n, "ebn0_db": points},
+               "info_gbit_s": round(fps * rmd.code_dimension(m, r) / 1e9, 4), "fer": fers, "roofline": roof,
+               "roofline_note": None if ops is not None else ops_src, "cpu_baseline": None}
+        print(json.dumps(out), flush=True)
+        dec.close()
 
 
 if __name__ == "__main__":
