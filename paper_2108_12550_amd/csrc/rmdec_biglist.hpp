@@ -134,6 +134,8 @@ __device__ __forceinline__ float big_g(float a, float b, uint32_t c) { return b 
 constexpr uint64_t kKeyPad = 0x7FF0000000000000ull;
 __device__ __forceinline__ double key_d(uint64_t k) { return __longlong_as_double((long long)k); }
 __device__ __forceinline__ uint64_t d_key(double d) { return (uint64_t)__double_as_longlong(d); }
+// smallest key over aligned groups of 2W lanes, the same in each lane (DPP
+// and swizzle butterflies; bfly_max, the largest, is the batched kernels')
 template <int W>
 __device__ __forceinline__ double bfly_min(double v)
 {
@@ -143,18 +145,6 @@ __device__ __forceinline__ double bfly_min(double v)
         return v;
 }
 
-// largest / smallest key over aligned groups of G lanes (DPP and swizzle
-// butterflies)
-template <int G>
-__device__ __forceinline__ uint64_t group_umax(uint64_t v)
-{
-    return d_key(bfly_max<G / 2>(key_d(v)));
-}
-template <int G>
-__device__ __forceinline__ uint64_t group_umin(uint64_t v)
-{
-    return d_key(bfly_min<G / 2>(key_d(v)));
-}
 // row broadcast (DPP): rows whose bit is set in RM take lane CTRL's value
 // from the row below (row_bcast:15 = 0x142, row_bcast:31 = 0x143); the
 // other rows keep their own
