@@ -120,3 +120,19 @@ def test_large_list_sampled_launch():
     idx = np.sort(np.random.default_rng(7).choice(n, 24, replace=False))
     od = oracle.OracleDecoder(9, 4, 1, 32, seed=0)
     assert_parity((bits[idx], pm[idx]), od.decode_batch(llr[idx], n_threads=THREADS), "sampled")
+
+
+def test_bench_launch_rm38_l64_sampled():
+    """The launch the large-list benchmark times: RM(3,8), one decoder with
+    L = 64 (Table 5's p-FHT-FSCL-64), 32768 frames at 3.0 dB: every output a
+    codeword, sampled frames against the oracle."""
+    n = 32768
+    _, llr = synth.frames(8, 3, n, 3.0, seed=31)
+    print("case sampled RM(3,8) P=1 L=64 n=32768", flush=True)
+    bits, pm = gpu_decode(8, 3, 1, 64, 0, PFHT, llr)
+    h = torch.from_numpy(synth.monomial_table(8, 8 - 3 - 1).astype(np.float32)).cuda()
+    xb = torch.from_numpy(synth.unpack_bits(bits, 256).astype(np.float32)).cuda()
+    assert int(torch.remainder(xb @ h.T, 2.0).sum().item()) == 0
+    idx = np.sort(np.random.default_rng(31).choice(n, 32, replace=False))
+    od = oracle.OracleDecoder(8, 3, 1, 64, seed=0)
+    assert_parity((bits[idx], pm[idx]), od.decode_batch(llr[idx], n_threads=THREADS), "bench launch sample")
