@@ -1387,6 +1387,17 @@ __device__ __forceinline__ void decode_batch_frame(const KernelArgs &args, int64
                              args.out_pm ? args.out_pm + f : nullptr, slice, lane);
 }
 
+// Workgroups are dealt round-robin over the 8 XCDs.  Numbered this way, the
+// workgroups of one XCD take consecutive frames, whose codewords and metrics
+// then fill 128-byte lines in one L2 instead of being written back in parts
+// by several (a bijection on [0, nb) whatever the dispatch order).
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb)
+{
+    constexpr int64_t X = 8;
+    const int64_t q = nb / X, r = nb % X, x = b % X, i = b / X;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 // ---------------------------------------------------------------------------
 // batched kernel: one wave per frame (grid-stride)
 // ---------------------------------------------------------------------------
@@ -1396,7 +1407,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
     using Sh = Shape<M, R, L, D>;
     const int wave = (int)(threadIdx.x / kWave);
     const int64_t stride = (int64_t)gridDim.x * args.waves;
-    for (int64_t f = (int64_t)blockIdx.x * args.waves + wave; f < args.n_frames; f += stride) {
+    for (int64_t f = xcd_block(blockIdx.x, gridDim.x) * args.waves + wave; f < args.n_frames; f += stride) {
         uint32_t tid; // opaque per frame: see rm_mixed_kernel
         asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"(threadIdx.x));
         decode_batch_frame<M, R, L, D>(args, f, rm_smem + (tid / kWave) * Sh::BYTES, (int)(tid & (kWave - 1)));
