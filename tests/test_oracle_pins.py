@@ -7,6 +7,7 @@ invariant of the decoder.  Runs on the CPU only.
 """
 import itertools
 import json
+import math
 import os
 from math import comb
 
@@ -413,3 +414,27 @@ def test_fer_matches_fig5_higher_orders(key, m, r, name, mode, L, ebn0, n):
     k = _fer(m, r, 1, L, mode, float(ebn0), n, seed=47)
     lo, hi = wilson(k, n, 3.29)
     assert lo <= pub <= hi, (key, name, ebn0, k / n, pub)
+
+
+def _two_digits(x):
+    e = math.floor(math.log10(x))
+    return round(x / 10 ** e, 1) * 10 ** e
+
+
+@pytest.mark.parametrize("key,r,m,M", [("RM(2,8) p-FHT-FSCL-1-25", 2, 8, 25), ("RM(2,9) p-FHT-FSCL-1-100", 2, 9, 100)])
+def test_op_count_reproduces_table5(key, r, m, M):
+    # Table 2's per-function counts summed over Alg. 2's node schedule give
+    # Table 5's complexity of p-FHT-FSCL-1-M, to the two digits printed
+    from oracle import complexity
+    got = complexity.ops_per_frame(r, m, 1, M)
+    assert _two_digits(got) == pytest.approx(GOLDEN["table5_complexity"][key], rel=1e-9)
+
+
+def test_op_count_per_function_at_a_node():
+    # one decoder of RM(2,9), L = 1: f and g at the six internal nodes
+    # (2^8 + ... + 2^3 each), FHT leaves 2^s (s + 1) for s = 8..3, one SPC
+    # leaf of 8 -- written out from the tree of Fig. 4's construction
+    from oracle import complexity
+    fg = sum(2 * (1 << (s - 1)) for s in range(4, 10))
+    fht = sum((1 << s) * (s + 1) for s in range(3, 9))
+    assert complexity.ops_per_decoder(2, 9, 1) == fg + fht + 8 == 5096
