@@ -102,6 +102,9 @@ rm_decoder *rm_decoder_create_ex(const rm_config *cfg);
  * RM_PERM_FRESH mode also on each frame's index within the call.
  */
 int rm_decode_batch(rm_decoder *d, const float *llr, int64_t n_frames, uint8_t *out_bits, float *out_metric);
+/* In RM_PERM_FRESH mode the decoder keeps one device buffer of map tables,
+ * redrawn for every chunk of frames; a call made on another stream than the
+ * previous call's first waits (on the device) for that call's decodes. */
 
 /* Release the decoder after the work queued on its stream completes.  NULL-safe. */
 void rm_decoder_destroy(rm_decoder *d);
@@ -137,6 +140,22 @@ int rm_perm_tables_frame(int m, int r, int P, int L, uint64_t seed, int perm_mod
 
 /* 1 if a kernel is built for (m, r, L, perm_mode), else 0.  Host only. */
 int rm_supported(int m, int r, int L, int perm_mode);
+
+/*
+ * Host only: information bits of decoded codewords (Section II-A).  A
+ * codeword of RM(r, m) is x = u G^{(x)m}, G = [[1,0],[1,1]], with u_i = 0 off
+ * the information set I = {i : popcount(i) >= m - r} (row weights 2^popcount(i)
+ * of at least the minimum distance 2^(m-r)); G^{(x)m} is its own inverse over
+ * GF(2), so u = x G^{(x)m}.  For each of n_frames codewords in the packed
+ * layout of rm_decode_batch's out_bits (host memory, N/8 bytes per frame)
+ * this writes u_I to `info` (host, K bytes per frame, one 0/1 value per
+ * byte, I in increasing order, K = sum_{i<=r} C(m, i)).  If `n_invalid` is
+ * not NULL it receives the number of frames whose u is not zero off I (not
+ * codewords of RM(r, m)); their info bytes are still written.  Returns RM_OK,
+ * or RM_E_INVAL for m, r outside 3 <= m <= 16, 1 <= r <= m-1, n_frames < 0 or
+ * a NULL array with n_frames > 0.
+ */
+int rm_codeword_to_info(int m, int r, const uint8_t *codewords, int64_t n_frames, uint8_t *info, int64_t *n_invalid);
 
 /* Message of the last error on this thread ("" if none). */
 const char *rm_last_error(void);

@@ -17,12 +17,12 @@ from ._lib import (RM_E_AGAIN, RM_E_HIP, RM_E_INVAL, RM_E_NOMEM, RM_E_PTR, RM_E_
                    rm_decoder_create_ex, rm_decoder_destroy, rm_decoder_info, rm_decoder_set_stream, rm_last_error,
                    rm_mixed_autotune, rm_mixed_capture, rm_mixed_create, rm_mixed_decode, rm_mixed_destroy,
                    rm_mixed_replay, rm_mixed_set_grid, rm_mixed_set_stream, rm_mixed_supported, rm_mixed_tuning,
-                   rm_perm_tables, rm_perm_tables_frame, rm_request, rm_segment, rm_server_config, rm_server_create, rm_server_destroy,
+                   rm_codeword_to_info, rm_perm_tables, rm_perm_tables_frame, rm_request, rm_segment, rm_server_config, rm_server_create, rm_server_destroy,
                    rm_server_now_us, rm_server_pending, rm_server_poll, rm_server_register_pool, rm_server_run_trace,
                    rm_server_submit, rm_server_supported, rm_supported)
 
 __all__ = ["Decoder", "MixedLauncher", "perm_tables", "code_dimension", "RM_PERM_NONE", "RM_PERM_PFHT",
-           "RM_PERM_FRESH", "rm_perm_tables_frame",
+           "RM_PERM_FRESH", "rm_perm_tables_frame", "rm_codeword_to_info", "codeword_to_info",
            "RM_MIXED_MAX_SEGMENTS", "rm_config", "rm_segment", "rm_decode_batch", "rm_decoder_create",
            "rm_decoder_create_ex", "rm_decoder_destroy", "rm_decoder_info", "rm_decoder_set_stream",
            "rm_last_error", "rm_perm_tables", "rm_supported", "rm_mixed_create", "rm_mixed_supported",
@@ -35,6 +35,18 @@ __all__ = ["Decoder", "MixedLauncher", "perm_tables", "code_dimension", "RM_PERM
 
 def code_dimension(m: int, r: int) -> int:
     return sum(comb(m, i) for i in range(r + 1))
+
+
+def codeword_to_info(m: int, r: int, codewords):
+    """Information bits u_I of packed codewords ((n, N/8) uint8 host array):
+    returns ((n, K) uint8, number of frames that are not codewords)."""
+    import numpy as np
+    cw = np.ascontiguousarray(codewords, dtype=np.uint8).reshape(-1, (1 << m) // 8)
+    out = np.zeros((cw.shape[0], code_dimension(m, r)), dtype=np.uint8)
+    rc, bad = rm_codeword_to_info(m, r, cw.ctypes.data, cw.shape[0], out.ctypes.data)
+    if rc != RM_OK:
+        raise RMError(rc, rm_last_error())
+    return out, bad
 
 
 class RMError(RuntimeError):

@@ -24,7 +24,7 @@ RM_PERM_PFHT = 1
 RM_PERM_FRESH = 2
 
 EXPORTED = ("rm_decoder_create", "rm_decoder_create_ex", "rm_decode_batch", "rm_decoder_destroy",
-            "rm_decoder_set_stream", "rm_decoder_info", "rm_perm_tables", "rm_perm_tables_frame", "rm_supported",
+            "rm_decoder_set_stream", "rm_decoder_info", "rm_perm_tables", "rm_perm_tables_frame", "rm_supported", "rm_codeword_to_info",
             "rm_last_error",
             "rm_mixed_create", "rm_mixed_supported", "rm_mixed_set_stream", "rm_mixed_set_grid", "rm_mixed_decode",
             "rm_mixed_capture", "rm_mixed_replay", "rm_mixed_autotune", "rm_mixed_destroy",
@@ -110,6 +110,8 @@ def load() -> ctypes.CDLL:
                                        P(ctypes.c_int), ctypes.c_int]
     L.rm_supported.restype = ctypes.c_int
     L.rm_supported.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.rm_codeword_to_info.restype = ctypes.c_int
+    L.rm_codeword_to_info.argtypes = [ctypes.c_int, ctypes.c_int, vp, ctypes.c_int64, vp, P(ctypes.c_int64)]
     L.rm_last_error.restype = ctypes.c_char_p
     L.rm_last_error.argtypes = []
     L.rm_mixed_create.restype = vp
@@ -202,6 +204,13 @@ def rm_perm_tables_frame(m: int, r: int, P: int, L: int, seed: int, perm_mode: i
 
 def rm_supported(m: int, r: int, L: int, perm_mode: int) -> bool:
     return bool(load().rm_supported(m, r, L, perm_mode))
+
+
+def rm_codeword_to_info(m: int, r: int, codewords_ptr: int, n_frames: int, info_ptr: int):
+    """Host arrays by address; returns (rc, number of frames that are not codewords)."""
+    bad = ctypes.c_int64(0)
+    rc = load().rm_codeword_to_info(m, r, codewords_ptr, n_frames, info_ptr, ctypes.byref(bad))
+    return rc, bad.value
 
 
 def rm_mixed_create(max_tiles: int) -> int:

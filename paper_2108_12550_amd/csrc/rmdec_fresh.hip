@@ -210,6 +210,14 @@ __global__ void __launch_bounds__(256) rm_fresh_maps_kernel(FreshArgs a)
 int fresh_decode(rm_decoder *d, const float *llr, int64_t n_frames, uint8_t *out_bits, float *out_metric)
 {
     const int64_t per_frame = (int64_t)d->cfg.P * d->maps_per_dec * kMapWords;
+    // The table buffer is shared by every call: a decode queued earlier on
+    // another stream may still read it, so the first draw waits for the last
+    // decode that used it (within a call, stream order does the same).
+    if (d->fresh_pending) {
+        const hipError_t w = hipStreamWaitEvent(d->stream, d->fresh_done, 0);
+        if (w != hipSuccess)
+            return fail(RM_E_HIP, std::string("fresh-mode stream wait: ") + hipGetErrorString(w));
+    }
     for (int64_t f0 = 0; f0 < n_frames; f0 += d->fresh_chunk) {
         const int64_t nf = n_frames - f0 < d->fresh_chunk ? n_frames - f0 : d->fresh_chunk;
         FreshArgs g;
@@ -231,6 +239,10 @@ int fresh_decode(rm_decoder *d, const float *llr, int64_t n_frames, uint8_t *out
             a.frame_stride = per_frame;
             const int blocks = (int)((nf + a.waves - 1) / a.waves);
             e = d->kern->launch(a, blocks, d->stream);
+        }
+        if (e == hipSuccess) {
+            e = hipEventRecord(d->fresh_done, d->stream);
+            d->fresh_pending = d->fresh_pending || e == hipSuccess;
         }
         if (e != hipSuccess)
             return fail(RM_E_HIP, std::string("fresh-mode launch: ") + hipGetErrorString(e));

@@ -287,6 +287,42 @@ int rm_supported(int m, int r, int L, int perm_mode)
     return find_kernel(m, r, L) != nullptr;
 }
 
+int rm_codeword_to_info(int m, int r, const uint8_t *codewords, int64_t n_frames, uint8_t *info, int64_t *n_invalid)
+{
+    if (m < 3 || m > 16 || r < 1 || r > m - 1)
+        return fail(RM_E_INVAL, "need 3 <= m <= 16 and 1 <= r <= m-1");
+    if (n_frames < 0)
+        return fail(RM_E_INVAL, "n_frames < 0");
+    if (n_frames > 0 && (!codewords || !info))
+        return fail(RM_E_INVAL, "null array");
+    const int N = 1 << m;
+    std::vector<uint8_t> u(N);
+    int64_t bad = 0;
+    for (int64_t f = 0; f < n_frames; f++) {
+        const uint8_t *x = codewords + f * (N / 8);
+        for (int i = 0; i < N; i++)
+            u[i] = (uint8_t)((x[i >> 3] >> (i & 7)) & 1u);
+        // u = x G^{(x)m}: per stage, the first of each pair (i, i + h) takes
+        // the XOR of both (G's lower-left 1), the second is kept
+        for (int h = 1; h < N; h <<= 1)
+            for (int i = 0; i < N; i += 2 * h)
+                for (int j = i; j < i + h; j++)
+                    u[j] ^= u[j + h];
+        uint8_t *o = info + f * binom_sum(m, r);
+        int k = 0, frozen = 0;
+        for (int i = 0; i < N; i++) {
+            if (__builtin_popcount((unsigned)i) >= m - r)
+                o[k++] = u[i];
+            else
+                frozen |= u[i];
+        }
+        bad += frozen != 0;
+    }
+    if (n_invalid)
+        *n_invalid = bad;
+    return RM_OK;
+}
+
 int rm_perm_tables(int m, int r, int P, int L, uint64_t seed, int perm_mode, uint16_t *rows, uint16_t *b, int *mdim,
                    int cap)
 {
@@ -390,6 +426,9 @@ rm_decoder *rm_decoder_create_ex(const rm_config *cfg)
     dec->stream = nullptr;
     dec->table_bytes = host.size() * sizeof(uint32_t);
     dec->fresh_chunk = 0;
+    dec->fresh_done = nullptr;
+    dec->fresh_pending = false;
+    dec->d_maps = nullptr;
     if (fresh) {
         // the tables of up to 16384 frames at a time (enough waves to fill the
         // chip), at most 512 MiB
@@ -438,10 +477,14 @@ rm_decoder *rm_decoder_create_ex(const rm_config *cfg)
         e = hipMalloc((void **)&dec->d_maps, dec->table_bytes);
     if (e == hipSuccess && !fresh)
         e = hipMemcpy(dec->d_maps, host.data(), dec->table_bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess && fresh)
+        e = hipEventCreateWithFlags(&dec->fresh_done, hipEventDisableTiming);
     if (e != hipSuccess) {
         fail(RM_E_HIP, std::string("HIP error at create: ") + hipGetErrorString(e));
         if (dec->d_maps)
             (void)hipFree(dec->d_maps);
+        if (dec->fresh_done)
+            (void)hipEventDestroy(dec->fresh_done);
         delete dec;
         return nullptr;
     }
@@ -460,6 +503,11 @@ void rm_decoder_destroy(rm_decoder *d)
     if (!d)
         return;
     (void)hipStreamSynchronize(d->stream);
+    if (d->fresh_done) {
+        // the last fresh-mode decode may have run on another stream
+        (void)hipEventSynchronize(d->fresh_done);
+        (void)hipEventDestroy(d->fresh_done);
+    }
     (void)hipFree(d->d_maps);
     delete d;
 }

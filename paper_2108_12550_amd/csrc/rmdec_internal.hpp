@@ -15,6 +15,11 @@ struct rm_decoder {
     uint32_t *d_maps;   // the map tables (fresh mode: one chunk of frames' tables)
     size_t table_bytes;
     int64_t fresh_chunk; // fresh mode: frames whose tables the buffer holds
+    // fresh mode: recorded after each chunk's decode on the stream it ran on;
+    // the next map draw waits on it, so tables still being read by a decode
+    // queued on another stream are never overwritten
+    hipEvent_t fresh_done;
+    bool fresh_pending;
     hipStream_t stream;
     int device;
 };

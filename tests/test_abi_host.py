@@ -217,3 +217,33 @@ def test_selection_keys_order_as_doubles():
     assert np.array_equal(a == b, da == db)
     pad = np.array([0x7FF0000000000000], dtype=np.uint64).view(np.float64)[0]
     assert np.all(da < pad) and np.all(keys < np.uint64(0x7FF0000000000000))
+
+
+@pytest.mark.parametrize("m,r", [(7, 2), (9, 2), (8, 3), (5, 1), (4, 3), (10, 2)])
+def test_codeword_to_info_inverts_the_oracle_encoder(m, r):
+    """rm_codeword_to_info against the oracle's own x = u G^{(x)m} encoder:
+    random u on the information set, frozen positions zero."""
+    rng = np.random.default_rng(m * 10 + r)
+    iset = oracle.info_set(m, r).astype(bool)
+    n = 20
+    u = np.zeros((n, 1 << m), np.uint8)
+    u[:, iset] = rng.integers(0, 2, size=(n, int(iset.sum())))
+    x = np.stack([oracle.encode(m, row) for row in u])
+    info, bad = rmd.codeword_to_info(m, r, np.packbits(x, axis=-1, bitorder="little"))
+    assert bad == 0
+    assert info.shape == (n, rmd.code_dimension(m, r))
+    assert np.array_equal(info, u[:, iset])
+
+
+def test_codeword_to_info_flags_non_codewords():
+    import synth
+    x, _ = synth.frames(9, 2, 16, 3.0, seed=4)  # codewords (polynomial evaluations)
+    cw = np.packbits(x, axis=-1, bitorder="little")
+    _, bad = rmd.codeword_to_info(9, 2, cw)
+    assert bad == 0
+    cw[3, 5] ^= 0x10  # one flipped bit: weight-1 error, not a codeword
+    cw[7, 0] ^= 0x01
+    _, bad = rmd.codeword_to_info(9, 2, cw)
+    assert bad == 2
+    rc, _ = _lib.rm_codeword_to_info(9, 9, cw.ctypes.data, 1, cw.ctypes.data)
+    assert rc == rmd.RM_E_INVAL

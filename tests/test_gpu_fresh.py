@@ -125,3 +125,37 @@ def test_fresh_full_size_sampled():
         x, p = od.decode(llr[f], frame=f)
         assert np.array_equal(synth.unpack_bits(bits[f:f + 1], 512)[0], x), f"frame {f}"
         assert abs(pm[f] - p) <= PM_RTOL * max(1.0, abs(p)), f"frame {f}"
+
+
+def test_fresh_two_streams_in_flight():
+    """Two calls of one fresh-mode decoder queued on two streams with no host
+    synchronisation between them: the second call's map draw must wait for
+    the first call's decode, which still reads the shared table buffer.
+    Each result equals the same call made alone."""
+    m, r, P, L = 9, 2, 20, 4
+    _, a = synth.frames(m, r, 40000, 2.5, seed=91)  # three table chunks
+    _, b = synth.frames(m, r, 20000, 2.5, seed=92)
+    print("case fresh two streams RM(2,9) P=20 L=4 n=40000+20000", flush=True)
+    ta, tb = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    dec = rmd.Decoder(m, r, P, L, seed=4, perm_mode=FRESH)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    ba, pa = dec.decode(ta, stream=s1)
+    bb, pb = dec.decode(tb, stream=s2)
+    torch.cuda.synchronize()
+    got_a, got_b = (ba.cpu().numpy(), pa.cpu().numpy()), (bb.cpu().numpy(), pb.cpu().numpy())
+    ra = dec.decode(ta)
+    torch.cuda.synchronize()
+    rb_ = dec.decode(tb)
+    torch.cuda.synchronize()
+    dec.close()
+    assert np.array_equal(got_a[0], ra[0].cpu().numpy()) and np.array_equal(got_a[1], ra[1].cpu().numpy())
+    assert np.array_equal(got_b[0], rb_[0].cpu().numpy()) and np.array_equal(got_b[1], rb_[1].cpu().numpy())
+    # and a sample of each against the oracle
+    od = oracle.OracleDecoder(m, r, P, L, seed=4, perm_mode=oracle.PERM_FRESH)
+    for f in (0, 16383, 16384, 39999):
+        x, p = od.decode(a[f], frame=f)
+        assert np.array_equal(synth.pack_bits(x), got_a[0][f])
+    for f in (0, 19999):
+        x, p = od.decode(b[f], frame=f)
+        assert np.array_equal(synth.pack_bits(x), got_b[0][f])
