@@ -248,6 +248,26 @@ int rm_mixed_autotune(rm_mixed *mx, const rm_segment *segs, int n_segs, int reps
 void rm_mixed_destroy(rm_mixed *mx);
 
 /*
+ * For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the fused
+ * launch of rm_mixed_decode with no launcher object and no allocation.  The
+ * queue entries and the queue head live in a static device array of the
+ * library (256 B + 16 B x RM_MIXED_STATIC_MAX_TILES = 8 MiB, held on every
+ * device the library runs on until the process ends).  Queues on
+ * `hip_stream` (a hipStream_t as void*, NULL = null stream) one small kernel
+ * that writes the queue and clears the head, then the persistent decode
+ * kernel (waves_per_block 0..4, 0 = 2; the grid is the occupancy limit).
+ * Per frame the result is exactly that of rm_mixed_decode and of
+ * rm_decode_batch.  Segments follow rm_mixed_decode's rules; more queue
+ * entries than RM_MIXED_STATIC_MAX_TILES give RM_E_INVAL and nothing is
+ * queued.  Every call on one device shares that device's array: calls that
+ * may overlap on one device (other streams, or another host thread) race and
+ * must be ordered by the caller.  Calls no hipMalloc or hipFree.
+ */
+#define RM_MIXED_STATIC_MAX_TILES (1 << 19)
+int rm_mixed_decode_static(const rm_segment *segs, int n_segs, int waves_per_block, void *hip_stream);
+
+/*
  * Request server: continuous batching of single-frame requests of any code,
  * P and L that a serving kernel is built for (rm_server_supported).
  *

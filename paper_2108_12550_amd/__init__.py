@@ -15,7 +15,8 @@ from . import _lib
 from ._lib import (RM_E_AGAIN, RM_E_HIP, RM_E_INVAL, RM_E_NOMEM, RM_E_PTR, RM_E_UNSUPPORTED, RM_MIXED_MAX_SEGMENTS,
                    RM_OK, RM_PERM_FRESH, RM_PERM_NONE, RM_PERM_PFHT, rm_completion, rm_config, rm_decode_batch, rm_decoder_create,
                    rm_decoder_create_ex, rm_decoder_destroy, rm_decoder_info, rm_decoder_set_stream, rm_last_error,
-                   rm_mixed_autotune, rm_mixed_capture, rm_mixed_create, rm_mixed_decode, rm_mixed_destroy,
+                   rm_mixed_autotune, rm_mixed_capture, rm_mixed_create, rm_mixed_decode, rm_mixed_decode_static,
+                   rm_mixed_destroy, RM_MIXED_STATIC_MAX_TILES,
                    rm_mixed_replay, rm_mixed_set_grid, rm_mixed_set_stream, rm_mixed_supported, rm_mixed_tuning,
                    rm_codeword_to_info, rm_perm_tables, rm_perm_tables_frame, rm_request, rm_segment, rm_server_config, rm_server_create, rm_server_destroy,
                    rm_server_now_us, rm_server_pending, rm_server_poll, rm_server_register_pool, rm_server_run_trace,
@@ -28,6 +29,7 @@ __all__ = ["Decoder", "MixedLauncher", "perm_tables", "code_dimension", "RM_PERM
            "rm_last_error", "rm_perm_tables", "rm_supported", "rm_mixed_create", "rm_mixed_supported",
            "rm_mixed_set_stream", "rm_mixed_set_grid", "rm_mixed_decode", "rm_mixed_capture",
            "rm_mixed_replay", "rm_mixed_autotune", "rm_mixed_tuning", "rm_mixed_destroy", "Server",
+           "rm_mixed_decode_static", "mixed_decode_static", "RM_MIXED_STATIC_MAX_TILES",
            "RM_E_AGAIN", "rm_server_config", "rm_request", "rm_completion", "rm_server_create",
            "rm_server_supported", "rm_server_now_us", "rm_server_register_pool", "rm_server_submit",
            "rm_server_poll", "rm_server_pending", "rm_server_run_trace", "rm_server_destroy"]
@@ -133,7 +135,8 @@ class MixedLauncher:
     def set_grid(self, blocks: int, waves_per_block: int):
         self._check(rm_mixed_set_grid(self._h, blocks, waves_per_block))
 
-    def _segs(self, segments):
+    @staticmethod
+    def _segs(segments):
         import torch
         out = []
         for dec, llr, bits, metric, tf in segments:
@@ -183,6 +186,19 @@ class MixedLauncher:
 
     def __del__(self):
         self.close()
+
+
+def mixed_decode_static(segments, waves_per_block: int = 0, stream=None):
+    """The fused launch of ``MixedLauncher.decode`` without a launcher: no
+    device allocation (rm_mixed_decode_static).  Segments as for
+    ``MixedLauncher``; calls on one device share the library's static queue,
+    so calls that may overlap must be ordered by the caller."""
+    import torch
+    segs = MixedLauncher._segs(segments)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    rc = rm_mixed_decode_static(segs, waves_per_block, s.cuda_stream)
+    if rc != RM_OK:
+        raise RMError(rc, rm_last_error())
 
 
 class Server:

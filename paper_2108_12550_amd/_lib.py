@@ -27,11 +27,12 @@ EXPORTED = ("rm_decoder_create", "rm_decoder_create_ex", "rm_decode_batch", "rm_
             "rm_decoder_set_stream", "rm_decoder_info", "rm_perm_tables", "rm_perm_tables_frame", "rm_supported", "rm_codeword_to_info",
             "rm_last_error",
             "rm_mixed_create", "rm_mixed_supported", "rm_mixed_set_stream", "rm_mixed_set_grid", "rm_mixed_decode",
-            "rm_mixed_capture", "rm_mixed_replay", "rm_mixed_autotune", "rm_mixed_destroy",
+            "rm_mixed_capture", "rm_mixed_replay", "rm_mixed_autotune", "rm_mixed_destroy", "rm_mixed_decode_static",
             "rm_server_create", "rm_server_supported", "rm_server_now_us", "rm_server_register_pool",
             "rm_server_submit", "rm_server_poll", "rm_server_pending", "rm_server_run_trace", "rm_server_destroy")
 
 RM_MIXED_MAX_SEGMENTS = 8
+RM_MIXED_STATIC_MAX_TILES = 1 << 19
 
 
 class rm_config(ctypes.Structure):
@@ -125,6 +126,8 @@ def load() -> ctypes.CDLL:
     for f in ("rm_mixed_decode", "rm_mixed_capture"):
         getattr(L, f).restype = ctypes.c_int
         getattr(L, f).argtypes = [vp, P(rm_segment), ctypes.c_int]
+    L.rm_mixed_decode_static.restype = ctypes.c_int
+    L.rm_mixed_decode_static.argtypes = [P(rm_segment), ctypes.c_int, ctypes.c_int, vp]
     L.rm_mixed_replay.restype = ctypes.c_int
     L.rm_mixed_replay.argtypes = [vp]
     L.rm_mixed_autotune.restype = ctypes.c_int
@@ -238,6 +241,10 @@ def _segments(segs):
 
 def rm_mixed_decode(mx: int, segs) -> int:
     return load().rm_mixed_decode(mx, _segments(segs), len(segs))
+
+
+def rm_mixed_decode_static(segs, waves_per_block: int, stream_handle: int) -> int:
+    return load().rm_mixed_decode_static(_segments(segs), len(segs), waves_per_block, stream_handle or None)
 
 
 def rm_mixed_capture(mx: int, segs) -> int:

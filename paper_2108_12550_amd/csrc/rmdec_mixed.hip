@@ -4,6 +4,7 @@
 
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -106,18 +107,30 @@ void drop_graph(rm_mixed *mx)
     free_queue(mx->gq);
 }
 
-// Validate the segments, fill the per-segment kernel arguments and build the
-// queue entries: every segment cut into runs of tile_frames frames, the runs
-// of all segments interleaved round-robin.
-int prepare(rm_mixed *mx, const rm_segment *segs, int n_segs, MixedArgs &a, std::vector<Tile> &tiles)
+// Runs of the segments of one launch: segment i is cut into runs[i] runs of
+// tf[i] frames (the last may be shorter); the runs of all segments are
+// interleaved round-robin, run q of every segment that has one, in segment
+// order, before run q + 1 of any.
+struct Runs {
+    int64_t runs[kMaxSegments];
+    int64_t n_frames[kMaxSegments];
+    uint32_t tf[kMaxSegments];
+    int n_segs;
+    int64_t total, longest;
+};
+
+// Validate the segments and fill the per-segment kernel arguments and runs.
+int check_segments(const rm_segment *segs, int n_segs, MixedArgs &a, Runs &ru)
 {
-    if (!mx || !segs)
+    if (!segs)
         return fail(RM_E_INVAL, "null argument");
     if (n_segs < 1 || n_segs > RM_MIXED_MAX_SEGMENTS)
         return fail(RM_E_INVAL, "n_segs must be in [1, RM_MIXED_MAX_SEGMENTS]");
     memset(&a, 0, sizeof a);
-    std::vector<int64_t> runs(n_segs);
-    std::vector<int> tf(n_segs);
+    memset(&ru, 0, sizeof ru);
+    ru.n_segs = n_segs;
+    int64_t *runs = ru.runs;
+    uint32_t *tf = ru.tf;
     int64_t total = 0, longest = 0;
     for (int i = 0; i < n_segs; i++) {
         const rm_segment &g = segs[i];
@@ -132,9 +145,9 @@ int prepare(rm_mixed *mx, const rm_segment *segs, int n_segs, MixedArgs &a, std:
         const int slot = fused_slot(g.dec->cfg.m, g.dec->cfg.r, g.dec->cfg.L);
         if (slot < 0)
             return fail(RM_E_UNSUPPORTED, "code not compiled into the fused kernel");
-        tf[i] = g.tile_frames == 0 ? 4 : g.tile_frames;
-        if (tf[i] < 1 || tf[i] > 64)
-            return fail(RM_E_INVAL, "tile_frames must be in [1, 64]");
+        if (g.tile_frames < 0 || g.tile_frames > 64)
+            return fail(RM_E_INVAL, "tile_frames must be in [1, 64] (0: library default)");
+        tf[i] = g.tile_frames == 0 ? 4u : (uint32_t)g.tile_frames;
         if (g.n_frames > 0) {
             if (!g.llr || !g.out_bits)
                 return fail(RM_E_INVAL, "null llr or out_bits");
@@ -148,19 +161,34 @@ int prepare(rm_mixed *mx, const rm_segment *segs, int n_segs, MixedArgs &a, std:
         }
         a.seg[i] = batch_args(g.dec, g.llr, g.n_frames, g.out_bits, g.out_metric);
         a.code[i] = slot;
+        ru.n_frames[i] = g.n_frames;
         runs[i] = (g.n_frames + tf[i] - 1) / tf[i];
         total += runs[i];
         longest = runs[i] > longest ? runs[i] : longest;
     }
-    if (total > mx->q.cap)
+    ru.total = total;
+    ru.longest = longest;
+    return RM_OK;
+}
+
+// Validate, fill the kernel arguments and build the queue entries on the host.
+int prepare(rm_mixed *mx, const rm_segment *segs, int n_segs, MixedArgs &a, std::vector<Tile> &tiles)
+{
+    if (!mx)
+        return fail(RM_E_INVAL, "null launcher");
+    Runs ru;
+    int rc = check_segments(segs, n_segs, a, ru);
+    if (rc != RM_OK)
+        return rc;
+    if (ru.total > mx->q.cap)
         return fail(RM_E_INVAL, "more queue entries than the launcher was created for");
     tiles.clear();
-    tiles.reserve((size_t)total);
-    for (int64_t q = 0; q < longest; q++)
+    tiles.reserve((size_t)ru.total);
+    for (int64_t q = 0; q < ru.longest; q++)
         for (int i = 0; i < n_segs; i++)
-            if (q < runs[i]) {
-                const int64_t first = q * tf[i];
-                const int64_t cnt = segs[i].n_frames - first < tf[i] ? segs[i].n_frames - first : tf[i];
+            if (q < ru.runs[i]) {
+                const int64_t first = q * ru.tf[i];
+                const int64_t cnt = ru.n_frames[i] - first < ru.tf[i] ? ru.n_frames[i] - first : ru.tf[i];
                 tiles.push_back(Tile{(uint32_t)i, (uint32_t)first, (uint32_t)cnt, 0u});
             }
     a.n_tiles = (uint32_t)tiles.size();
@@ -168,18 +196,22 @@ int prepare(rm_mixed *mx, const rm_segment *segs, int n_segs, MixedArgs &a, std:
     return RM_OK;
 }
 
-int grid_blocks(rm_mixed *mx, int waves)
+// persistent grid: the blocks the device holds at once
+int occupancy_blocks(int device, int waves)
 {
-    if (mx->blocks)
-        return mx->blocks;
     int per_cu = 0, cus = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fused_kernel(), kWave * waves,
                                                                 (size_t)waves * kFusedBytes);
     if (e == hipSuccess)
-        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, mx->device);
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
     if (e != hipSuccess || per_cu < 1 || cus < 1)
         return 256 * 4;
     return per_cu * cus;
+}
+
+int grid_blocks(rm_mixed *mx, int waves)
+{
+    return mx->blocks ? mx->blocks : occupancy_blocks(mx->device, waves);
 }
 
 // Queue the head reset and the persistent kernel on the launcher's stream.
@@ -456,3 +488,122 @@ void rm_mixed_destroy(rm_mixed *mx)
 }
 
 } // extern "C"
+
+// ---------------------------------------------------------------------------
+// Fused launch that allocates nothing: the queue entries and the queue head
+// live in one statically sized device array instead of a launcher's buffers.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int64_t kStaticTiles = RM_MIXED_STATIC_MAX_TILES;
+constexpr int kHeadWords = 64; // the head counter, alone in the first 256 bytes
+// [head, pad .. ][Tile x kStaticTiles]: 256 B + 8 MiB on every device the library runs on
+__device__ __align__(256) uint32_t scratch[kHeadWords + kStaticTiles * (sizeof(Tile) / 4)];
+
+struct StaticFill {
+    int64_t runs[kMaxSegments];
+    int64_t n_frames[kMaxSegments];
+    uint32_t tf[kMaxSegments];
+    int n_segs;
+    int64_t longest;
+};
+
+// Writes the queue of check_segments' round-robin interleave (thread q: run q
+// of every segment that has one, at the entry after all runs of rounds < q)
+// and clears the head, so the fill and the decode can sit in a captured graph.
+__global__ void rm_fill_static_queue(StaticFill f, Tile *tiles, uint32_t *head)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q == 0)
+        *head = 0u;
+    if (q >= f.longest)
+        return;
+    int64_t k = 0;
+    for (int i = 0; i < f.n_segs; i++)
+        k += q < f.runs[i] ? q : f.runs[i];
+    for (int i = 0; i < f.n_segs; i++)
+        if (q < f.runs[i]) {
+            const int64_t first = q * f.tf[i];
+            const int64_t left = f.n_frames[i] - first;
+            tiles[k++] = Tile{(uint32_t)i, (uint32_t)first, (uint32_t)(left < f.tf[i] ? left : f.tf[i]), 0u};
+        }
+}
+
+// Device address of `scratch` on each device, looked up once per device with
+// that device current (each device holds its own copy of the array).
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+uint32_t *g_static_ptr[kMaxDevices];
+int g_static_blocks[kMaxDevices][5];
+
+int static_scratch(int device, int waves, uint32_t **ptr, int *blocks)
+{
+    if (device < 0 || device >= kMaxDevices)
+        return fail(RM_E_UNSUPPORTED, "device index beyond the library's table");
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(RM_E_HIP, std::string("scratch address: ") + hipGetErrorString(e));
+        g_static_ptr[device] = (uint32_t *)p;
+    }
+    if (!g_static_blocks[device][waves])
+        g_static_blocks[device][waves] = occupancy_blocks(device, waves);
+    *ptr = g_static_ptr[device];
+    *blocks = g_static_blocks[device][waves];
+    return RM_OK;
+}
+
+} // namespace
+
+extern "C" int rm_mixed_decode_static(const rm_segment *segs, int n_segs, int waves_per_block, void *hip_stream)
+{
+    if (waves_per_block < 0 || waves_per_block > 4)
+        return fail(RM_E_INVAL, "waves_per_block must be in [0, 4]");
+    const int waves = waves_per_block ? waves_per_block : 2;
+    if ((size_t)waves * kFusedBytes > 65536)
+        return fail(RM_E_UNSUPPORTED, "LDS slices do not fit the requested waves per block");
+    MixedArgs a;
+    Runs ru;
+    int rc = check_segments(segs, n_segs, a, ru);
+    if (rc != RM_OK)
+        return rc;
+    if (ru.total > kStaticTiles)
+        return fail(RM_E_INVAL, "more queue entries than RM_MIXED_STATIC_MAX_TILES (use larger tile_frames)");
+    if (ru.total == 0)
+        return RM_OK;
+    int device = 0;
+    hipError_t e = hipGetDevice(&device);
+    if (e != hipSuccess)
+        return fail(RM_E_HIP, std::string("current device: ") + hipGetErrorString(e));
+    uint32_t *base = nullptr;
+    int blocks = 0;
+    rc = static_scratch(device, waves, &base, &blocks);
+    if (rc != RM_OK)
+        return rc;
+    StaticFill f;
+    memset(&f, 0, sizeof f);
+    for (int i = 0; i < n_segs; i++) {
+        f.runs[i] = ru.runs[i];
+        f.n_frames[i] = ru.n_frames[i];
+        f.tf[i] = ru.tf[i];
+    }
+    f.n_segs = n_segs;
+    f.longest = ru.longest;
+    Tile *tiles = (Tile *)(base + kHeadWords);
+    const hipStream_t s = (hipStream_t)hip_stream;
+    hipLaunchKernelGGL(rm_fill_static_queue, dim3((unsigned)((ru.longest + 255) / 256)), dim3(256), 0, s, f, tiles,
+                       base);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(RM_E_HIP, std::string("queue fill: ") + hipGetErrorString(e));
+    a.tiles = tiles;
+    a.head = base;
+    a.n_tiles = (uint32_t)ru.total;
+    a.waves = waves;
+    e = launch_fused(a, blocks, s);
+    if (e != hipSuccess)
+        return fail(RM_E_HIP, std::string("fused launch: ") + hipGetErrorString(e));
+    return RM_OK;
+}
