@@ -1,25 +1,23 @@
 """Throughput benchmark of the batched p-FHT-FSCL-L-M decoder on one MI355X.
 
-Workload: RM(2,9) (N = 512, K = 46), P = 20 permuted decoders of list size
-L = 4 per frame, BPSK/AWGN frames at Eb/N0 = 2.0, 2.5, 3.0, 3.5, 4.0 dB,
-262,144 frames per Eb/N0 point.  One step decodes one point's batch (one
-kernel launch); steps cycle through the points.  All inputs are generated
-(seeded, synthetic) and copied to HBM before the timed region.
+Headline workload: RM(2,9) (N = 512, K = 46), P = 20 permuted decoders of
+list size L = 4 per frame, BPSK/AWGN frames at Eb/N0 = 2.0, 2.5, 3.0, 3.5,
+4.0 dB, 262,144 frames per Eb/N0 point.  One step decodes one point's batch
+(one kernel launch); steps cycle through the points.  All inputs are
+generated (seeded, synthetic) and copied to HBM before the timed region.
 
-With ``--workload mixed``: one fused persistent launch (graph-replayed) over
-RM(2,7) P=8, RM(2,8) P=16, RM(2,9) P=20 and RM(2,10) P=32, all L = 4, with
-262,144 frames each (1,048,576 per step), Eb/N0 uniform in [2, 4] dB per
-frame; launch choices come from the library's autotuner.
+The default run also measures, into extra keys of the same JSON line:
+"configs" -- RM(2,7) with one plain FHT-FSC decoder (FER on 10,000 frames,
+throughput on 2^21 frames against the HBM roofline), RM(2,9) with 512
+permuted decoders of list size 1 and RM(3,8) with 8 permuted decoders of list
+size 8 (131,072 frames per point, 2.0-4.5 dB, ALU rooflines); "mixed" -- the
+fused mixed-code launch (graph-replayed) over RM(2,7) P=8, RM(2,8) P=16,
+RM(2,9) P=20 and RM(2,10) P=32 at L = 4, with the launch choices of the
+library's autotuner; "serving" -- the request server at 0.5, 1, 2, 5, 10 and
+20 M requests/s.
 
-With ``--workload configs``: the other configurations of the evaluation,
-one JSON line each (decode rate, FER per Eb/N0 point, and the ALU roofline
-where the paper gives an operation count): RM(2,7) with one plain FHT-FSC
-decoder (10,000 frames at 3.0 dB), RM(2,9) with 512 permuted decoders of
-list size 1 and RM(3,8) with 8 permuted decoders of list size 8 (131,072
-frames per point, 2.0 to 4.5 dB).
-
-Prints one JSON line (one per configuration with ``--workload configs``).
-Diagnostics go to stderr.
+``--workload mixed|serve|biglist|configs`` prints only that part (one JSON
+line per configuration for ``configs``).  Diagnostics go to stderr.
 """
 from __future__ import annotations
 
@@ -92,6 +90,25 @@ def fer_ci(errors: int, n: int, z: float = 1.96):
             "ci95": [float(max(0.0, mid - half)), float(min(1.0, mid + half))]}
 
 
+def host_cpu():
+    """Threads the oracle may use (the CPU share of this process, at most 16
+    per GPU) and what the host reports about its processor."""
+    nproc = os.cpu_count() or 1
+    try:
+        share = len(os.sched_getaffinity(0))
+    except AttributeError:
+        share = nproc
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"threads": max(1, min(16, share)), "nproc": nproc, "affinity": share, "cpu_model": model}
+
+
 def cpu_baseline(llr_host: np.ndarray, gpu_bits: np.ndarray, budget_s: float, threads: int, perm_mode: int = 1):
     """The CPU oracle on a bounded sample of the same frames."""
     import oracle
@@ -106,9 +123,27 @@ def cpu_baseline(llr_host: np.ndarray, gpu_bits: np.ndarray, budget_s: float, th
         same &= bool(np.array_equal(bits, gpu_bits[sl]))
         done = sl.stop
     dt = time.perf_counter() - t0
+    h = host_cpu()
     return {"value": done / dt, "unit": "frames/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {done} frames of the 3.0 dB batch ({dt:.1f} s), {threads} threads, "
-                      f"bit-exact vs GPU: {same}"}, same
+            "per_core": done / dt / threads, "nproc": h["nproc"], "cpu_model": h["cpu_model"],
+            "sample": f"first {done} frames of the 3.0 dB batch ({dt:.1f} s): one single-threaded oracle decoder "
+                      f"per thread on {threads} threads (this process's CPU share: {h['affinity']} of "
+                      f"{h['nproc']} logical CPUs, at most 16 per GPU), bit-exact vs GPU: {same}"}, same
+
+
+def hip_ms(stream, fn, steps):
+    """Average milliseconds of fn() over `steps` calls, by HIP events recorded
+    on the stream the kernels run on."""
+    import torch
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(steps):
+        fn()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / max(1, steps)
 
 
 def main():
@@ -122,8 +157,10 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
     ap.add_argument("--workload", choices=("rm29", "mixed", "serve", "biglist", "configs"), default="rm29")
-    ap.add_argument("--serve-ms", type=float, default=100.0, help="arrival window per rate of the serving trace")
-    ap.add_argument("--no-serve", action="store_true", help="skip the serving section of the rm29 workload")
+    ap.add_argument("--serve-ms", type=float, default=50.0, help="arrival window per rate of the serving trace")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving part of the default run")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the RM(2,9) P=20 L=4 measurement (no configs, mixed or serving parts)")
     ap.add_argument("--fresh", action="store_true",
                     help="rm29 workload with maps drawn afresh for every frame (the draw is timed with the decode)")
     args = ap.parse_args()
@@ -134,14 +171,31 @@ def main():
         sys.exit(2)
 
     if args.workload == "mixed":
-        return run_mixed(args)
+        print(json.dumps(bench_mixed(args, with_cpu=not args.no_cpu_baseline)), flush=True)
+        return
     if args.workload == "serve":
         return run_serve(args)
     if args.workload == "biglist":
         return run_biglist(args)
     if args.workload == "configs":
-        return run_configs(args)
+        for rec in bench_configs(args):
+            print(json.dumps(rec), flush=True)
+        return
 
+    out = bench_headline(args)
+    if not args.headline_only:
+        import torch
+        torch.cuda.empty_cache()
+        out["configs"] = bench_configs(args)
+        torch.cuda.empty_cache()
+        out["mixed"] = bench_mixed(args, with_cpu=False)
+        torch.cuda.empty_cache()
+        if not args.no_serve:
+            out["serving"] = serve_sweep(SERVE_RATES, args.serve_ms)
+    print(json.dumps(out), flush=True)
+
+
+def bench_headline(args):
     import torch
     import paper_2108_12550_amd as rmd
     import synth
@@ -170,6 +224,7 @@ def main():
         with torch.cuda.stream(stream):
             dst.copy_(src)
         stream.synchronize()
+        del src, dst
         log("copy calibration: 1 GiB read + 1 GiB written")
 
     def step(i):
@@ -202,6 +257,8 @@ def main():
     log(f"FER per Eb/N0: {fer}")
     dec_bits_30 = outs[EBN0.index(3.0)][0].cpu().numpy()
     llr_30 = batches[EBN0.index(3.0)][1]
+    dec.close()
+    del batches, outs
 
     ops_per_launch = OPS_PER_FRAME * n
     achieved = ops_per_launch / (ms_per_step / 1e3) / 1e12
@@ -211,19 +268,13 @@ def main():
             "avg_launch_ms": round(ms_per_step, 4),
             "hbm_gbs_algorithmic": round((4 * 512 + 64 + 4) * fps / 1e9, 2)}
 
-    serving = None
-    if not args.no_serve:
-        del batches, outs
-        serving = serve_sweep(SERVE_RATES_SHORT, args.serve_ms / 2)
-
     cpu = None
     if not args.no_cpu_baseline:
-        gpu_bits = dec_bits_30
-        threads = min(16, os.cpu_count() or 1)
-        cpu, same = cpu_baseline(llr_30, gpu_bits, args.cpu_budget, threads, perm_mode=mode)
+        threads = host_cpu()["threads"]
+        cpu, same = cpu_baseline(llr_30, dec_bits_30, args.cpu_budget, threads, perm_mode=mode)
         log(f"cpu_baseline: {cpu}")
 
-    out = {
+    return {
         "metric": METRIC, "value": round(fps, 1), "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -236,9 +287,7 @@ def main():
         "fer": fer,
         "roofline": roof,
         "cpu_baseline": cpu,
-        "serving": serving,
     }
-    print(json.dumps(out), flush=True)
 
 
 # --- fused mixed-code launch -------------------------------------------------
@@ -275,7 +324,7 @@ def mixed_cpu_baseline(data, gpu_bits, budget_s, threads):
                       f"{threads} threads; bit-exact vs GPU: {same}"}, same
 
 
-def run_mixed(args):
+def bench_mixed(args, with_cpu=True):
     import torch
     import paper_2108_12550_amd as rmd
     import synth
@@ -351,11 +400,14 @@ def run_mixed(args):
             "kernel": MIXED_KERNEL, "avg_launch_ms": round(ms_fused, 4),
             "hbm_gbs_algorithmic": round(byts / (ms_fused / 1e3) / 1e9, 2)}
     cpu = None
-    if not args.no_cpu_baseline:
-        threads = min(16, os.cpu_count() or 1)
+    if with_cpu:
+        threads = host_cpu()["threads"]
         cpu, _ = mixed_cpu_baseline(data, gpu_bits, args.cpu_budget, threads)
         log(f"cpu_baseline: {cpu}")
     K = {m: synth.code_dimension(m, r) for m, r, *_ in MIXED_CODES}
+    for d in decs:
+        d.close()
+    mx.close()
     out = {
         "metric": METRIC, "value": round(fps, 1), "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_fused, 4), "higher_is_better": True, "scaling": "weak",
@@ -371,7 +423,7 @@ def run_mixed(args):
         "roofline": roof,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 # --- request server -----------------------------------------------------------
@@ -380,7 +432,6 @@ SERVE_WEIGHTS = [0.3, 0.25, 0.2, 0.15, 0.1]
 SERVE_P = [8, 20, 32]
 SERVE_L = [1, 4, 8]
 SERVE_RATES = [0.5, 1.0, 2.0, 5.0, 10.0, 20.0]  # M requests/s
-SERVE_RATES_SHORT = [1.0, 5.0]
 SERVE_POOL = 32768  # frames per code held in HBM; requests draw rows from it
 
 
@@ -497,7 +548,7 @@ def run_biglist(args):
             "avg_launch_ms": round(ms, 4), "hbm_gbs_algorithmic": round((4 * 256 + 32 + 4) * fps / 1e9, 3)}
     cpu = None
     if not args.no_cpu_baseline:
-        threads = min(16, os.cpu_count() or 1)
+        threads = host_cpu()["threads"]
         od = oracle.OracleDecoder(m, r, P, L, seed=SEED)
         done, same, t0 = 0, True, time.perf_counter()
         gb = bits.cpu().numpy()
@@ -518,29 +569,90 @@ def run_biglist(args):
     print(json.dumps(out), flush=True)
 
 
+# Operations per frame: the paper's counts (Section III-B, Tables 1-2)
+# summed over Alg. 2's node schedule -- exact at L = 1 (Fig. 6's L = 1
+# points and Table 5's p-FHT-FSCL-1-M column are reproduced by this count);
+# at L = 8 an approximate list-node model (within 6% of Fig. 6's list points).
+C1_OPS = 880.0          # RM(2,7), one plain FHT-FSC decoder: f/g 2^s per node, s 2^s per transform, 2^s per SPC node
+C1_BYTES = 4 * 128 + 128 // 8 + 4  # LLRs in, codeword and metric out
+C3A_OPS = 2614783.0     # RM(2,9), 512 decoders of list size 1 (exact count; Table 5 prints 5.1e5 for 100)
+C3B_OPS = 195015.0      # RM(3,8), 8 decoders of list size 8 (list-node model)
+C1_KERNEL = "rm_decode_packed_kernel<7, 2, 1, 8, 3>"
+C1_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rm_decode_rm27_p1_l1_traffic.txt")
+C1_SOURCES = [os.path.join(ROOT, "paper_2108_12550_amd", "csrc", f)
+              for f in ("rmdec_device.hpp", "rmdec_kernels.hpp", "rmdec_inst_b.hip")]
+C1_FRAMES = 1 << 21
+
 # (name, m, r, P, L, permutation mode, frames per point, Eb/N0 points,
-#  operations per frame or None, where they come from)
+#  operations per frame, where they come from, kernel)
 CONFIGS = [
-    ("RM(7,2) N=128 K=29 (paper's RM(2,7)), one plain FHT-FSC decoder (P=1, L=1, identity permutation)",
-     7, 2, 1, 1, "none", 10000, [3.0], None, "the paper gives no operation count for this decoder"),
     ("RM(9,2) N=512 K=46 (paper's RM(2,9)), P=512 permuted decoders, L=1",
-     9, 2, 512, 1, "pfht", 131072, [2.0, 2.5, 3.0, 3.5, 4.0, 4.5], 5.1e5 / 100 * 512,
-     "Table 5's p-FHT-FSCL-1-100 on RM(2,9), 5.1e5 per frame, scaled to 512 decoders"),
+     9, 2, 512, 1, "pfht", 131072, [2.0, 2.5, 3.0, 3.5, 4.0, 4.5], C3A_OPS,
+     "exact L = 1 count: 512 x 5107 + 511 (Table 5's p-FHT-FSCL-1-100, 5.1e5, is the same count for 100)",
+     "rm_decode_kernel<9, 2, 1, 8, 3>"),
     ("RM(8,3) N=256 K=93 (paper's RM(3,8)), P=8 permuted decoders, L=8",
-     8, 3, 8, 8, "pfht", 131072, [2.0, 2.5, 3.0, 3.5, 4.0, 4.5], None,
-     "the paper gives no operation count for p-FHT-FSCL-8-8"),
+     8, 3, 8, 8, "pfht", 131072, [2.0, 2.5, 3.0, 3.5, 4.0, 4.5], C3B_OPS,
+     "list-node model (parity unpinned; the paper prints no figure for p-FHT-FSCL-8-8)",
+     "rm_decode_kernel<8, 3, 8, 1, 3>"),
 ]
 
 
-def run_configs(args):
+def bench_c1(args, dev, stream):
+    """RM(2,7) with one plain FHT-FSC decoder: FER on the configuration's
+    10,000 frames (seed 0, 3.0 dB), throughput on 2^21 frames (1.07 GB of
+    LLRs, beyond the 256 MB last-level cache) against the HBM roofline."""
+    import torch
+    import paper_2108_12550_amd as rmd
+    import synth
+    m, r = 7, 2
+    N = 1 << m
+    dec = rmd.Decoder(m, r, 1, 1, seed=SEED, perm_mode=rmd.RM_PERM_NONE)
+    x, llr = synth.frames(m, r, 10000, 3.0, seed=0)
+    bits, _ = dec.decode(torch.from_numpy(llr).to(dev), stream=stream)
+    torch.cuda.synchronize()
+    fer = {"3.0": fer_ci(int(np.any(synth.unpack_bits(bits.cpu().numpy(), N) != x, axis=1).sum()), 10000)}
+    n = C1_FRAMES
+    _, big = synth.frames(m, r, n, 3.0, seed=1)
+    t = torch.from_numpy(big).to(dev)
+    del big
+    ob = torch.empty((n, N // 8), dtype=torch.uint8, device=dev)
+    op = torch.empty((n,), dtype=torch.float32, device=dev)
+
+    def step():
+        dec.decode(t, out_bits=ob, out_metric=op, stream=stream)
+
+    for _ in range(max(1, args.warmup)):
+        step()
+    reps = max(10, 2 * args.steps)
+    ms = hip_ms(stream, step, reps)
+    fps = n / (ms / 1e3)
+    gbs = C1_BYTES * fps / 1e9
+    log(f"RM(2,7) P=1 L=1: {fps / 1e9:.3f} G frames/s, {gbs:.0f} GB/s")
+    roof = {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": measured_traffic(C1_TRAFFIC_FILE, C1_SOURCES),
+            "kernel": C1_KERNEL, "avg_launch_ms": round(ms, 4), "bytes_per_frame": C1_BYTES,
+            "alu_frac": round(C1_OPS * fps / 1e12 / ALU_PEAK_TOPS, 5), "ops_per_frame": C1_OPS}
+    dec.close()
+    return {"metric": "frames/s", "value": round(fps, 1), "unit": "frames/s", "n_gpus": 1, "steps": reps,
+            "warmup": max(1, args.warmup), "ms_per_step": round(ms, 4), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "RM(7,2) N=128 K=29 (paper's RM(2,7)), one plain FHT-FSC decoder (P=1, L=1, "
+                                   "identity permutation), BPSK/AWGN 3.0 dB; FER on 10,000 frames from seed 0, "
+                                   "throughput on 2^21 frames from seed 1", "frames_per_step": n},
+            "info_gbit_s": round(fps * synth.code_dimension(m, r) / 1e9, 4), "fer": fer, "roofline": roof}
+
+
+def bench_configs(args):
     import torch
     import paper_2108_12550_amd as rmd
     import synth
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.Stream(device=dev)
+    recs = [bench_c1(args, dev, stream)]
+    torch.cuda.empty_cache()
     reps = max(1, min(args.steps, 3))
-    for name, m, r, P, L, mode, n, points, ops, ops_src in CONFIGS:
+    for name, m, r, P, L, mode, n, points, ops, ops_src, kname in CONFIGS:
         perm = rmd.RM_PERM_NONE if mode == "none" else rmd.RM_PERM_PFHT
         dec = rmd.Decoder(m, r, P, L, seed=SEED, perm_mode=perm)
         N = 1 << m
@@ -550,36 +662,30 @@ def run_configs(args):
         for k, e in enumerate(points):
             x, llr = synth.frames(m, r, n, e, seed=SEED + k)
             t = torch.from_numpy(llr).to(dev)
+
+            def step():
+                dec.decode(t, out_bits=bits, out_metric=pm, stream=stream)
+
             for _ in range(max(1, args.warmup)):
-                dec.decode(t, out_bits=bits, out_metric=pm, stream=stream)
-            torch.cuda.synchronize()
-            ev0 = torch.cuda.Event(enable_timing=True)
-            ev1 = torch.cuda.Event(enable_timing=True)
-            ev0.record(stream)
-            for _ in range(reps):
-                dec.decode(t, out_bits=bits, out_metric=pm, stream=stream)
-            ev1.record(stream)
-            torch.cuda.synchronize()
-            total_ms += ev0.elapsed_time(ev1) / reps
+                step()
+            total_ms += hip_ms(stream, step, reps)
             xb = synth.unpack_bits(bits.cpu().numpy(), N)
             fers[str(e)] = fer_ci(int(np.any(xb != x, axis=1).sum()), n)
-            log(f"{name.split(',')[0]}: {e} dB done")
         ms = total_ms / len(points)
         fps = n / (ms / 1e3)
-        roof = None
-        if ops is not None:
-            achieved = ops * fps / 1e12
-            roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(ALU_PEAK_TOPS, 4), "unit": "TFLOP/s",
-                    "frac": round(achieved / ALU_PEAK_TOPS, 5), "traffic": None, "ops_per_frame": ops,
-                    "ops_source": ops_src, "avg_launch_ms": round(ms, 4)}
-        out = {"metric": "frames/s", "value": round(fps, 1), "unit": "frames/s", "n_gpus": 1, "steps": reps,
-               "warmup": max(1, args.warmup), "ms_per_step": round(ms, 4), "higher_is_better": True,
-               "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-               "config": {"workload": name + ", BPSK/AWGN", "frames_per_point": n, "ebn0_db": points},
-               "info_gbit_s": round(fps * rmd.code_dimension(m, r) / 1e9, 4), "fer": fers, "roofline": roof,
-               "roofline_note": None if ops is not None else ops_src, "cpu_baseline": None}
-        print(json.dumps(out), flush=True)
+        log(f"{name.split(',')[0]} P={P} L={L}: {fps / 1e6:.3f} M frames/s")
+        achieved = ops * fps / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(ALU_PEAK_TOPS, 4), "unit": "TFLOP/s",
+                "frac": round(achieved / ALU_PEAK_TOPS, 5), "traffic": None, "ops_per_frame": ops,
+                "ops_source": ops_src, "kernel": kname, "avg_launch_ms": round(ms, 4)}
+        recs.append({"metric": "frames/s", "value": round(fps, 1), "unit": "frames/s", "n_gpus": 1, "steps": reps,
+                     "warmup": max(1, args.warmup), "ms_per_step": round(ms, 4), "higher_is_better": True,
+                     "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                     "config": {"workload": name + ", BPSK/AWGN", "frames_per_point": n, "ebn0_db": points},
+                     "info_gbit_s": round(fps * rmd.code_dimension(m, r) / 1e9, 4), "fer": fers, "roofline": roof})
         dec.close()
+        torch.cuda.empty_cache()
+    return recs
 
 
 if __name__ == "__main__":

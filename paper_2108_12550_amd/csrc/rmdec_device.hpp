@@ -343,6 +343,7 @@ template <int M, int R, int L, int D>
 struct Ctx {
     using S = Shape<M, R, L, D>;
     unsigned char *base;
+    uint32_t yoff; // byte offset of this decoder's channel LLRs from O_Y (frame-packed kernels)
     int lane, lg;
     int g;  // path within the decoder
     int gb; // first group of this lane's decoder
@@ -350,8 +351,8 @@ struct Ctx {
     int pfht;
     __device__ int lane_of(int path) const { return (gb + path) * S::G + lg; } // same element, other path
     __device__ int lead_of(int path) const { return (gb + path) * S::G; }      // first lane of a path
-    __device__ float *y() const { return (float *)(base + S::O_Y); }
-    __device__ uint32_t y_addr() const { return lds_addr(base) + S::O_Y; }
+    __device__ float *y() const { return (float *)(base + S::O_Y + yoff); }
+    __device__ uint32_t y_addr() const { return lds_addr(base) + S::O_Y + yoff; }
     __device__ uint32_t stage_addr() const { return lds_addr(base) + S::O_STAGE; }
     __device__ uint32_t *maps_all() const { return (uint32_t *)(base + S::O_MAPS); }
     __device__ uint32_t *maps() const { return maps_all() + ds * S::MAPS_PER_DEC * kMapWords; }
@@ -1247,6 +1248,7 @@ __device__ __forceinline__ Ctx<M, R, L, D> frame_ctx(const KernelArgs &args, uns
     constexpr int G = Sh::G;
     Ctx<M, R, L, D> c;
     c.base = slice;
+    c.yoff = 0;
     c.lane = lane;
     // lane is in [0, 64): unsigned division and remainder are shifts and masks
     const uint32_t ul = (uint32_t)lane, gw = ul / G;
@@ -1321,17 +1323,16 @@ __device__ __forceinline__ FrameBest decode_decoders(const KernelArgs &args, con
     return {best, bestmap};
 }
 
+// Writes the codeword whose masks (row layout of the root, 2G words) are at
+// xb, taken back to channel order by the map at mi, and the metric `best`.
 template <int M, int R, int L, int D>
-__device__ __forceinline__ void emit_codeword(const KernelArgs &args, const uint32_t *maps, FrameBest fb, uint8_t *ob,
-                                              float *opm, unsigned char *slice, int lane)
+__device__ __forceinline__ void emit_masks(const uint32_t *mi, float best, const uint64_t *xb, uint8_t *ob, float *opm,
+                                           int lane)
 {
     using Sh = Shape<M, R, L, D>;
     constexpr int N = Sh::N;
     constexpr int G = Sh::G;
-    const Ctx<M, R, L, D> c = frame_ctx<M, R, L, D>(args, slice, lane);
-    const uint64_t *xb = c.xbest();
     // the winner back in channel order, packed
-    const uint32_t *mi = maps + (size_t)fb.bestmap * kMapWords;
     uint32_t col[M + 1];
 #pragma unroll
     for (int k = 0; k < M; k++)
@@ -1339,7 +1340,7 @@ __device__ __forceinline__ void emit_codeword(const KernelArgs &args, const uint
     col[M] = mi[kMapB] >> 2;
 #pragma unroll
     for (int j0 = 0; j0 < N; j0 += kWave) {
-        const uint32_t j = (uint32_t)(j0 + c.lane);
+        const uint32_t j = (uint32_t)(j0 + lane);
         uint32_t e = col[M];
 #pragma unroll
         for (int k = 0; k < M; k++)
@@ -1358,15 +1359,23 @@ __device__ __forceinline__ void emit_codeword(const KernelArgs &args, const uint
         }
         const uint64_t mask = __ballot(bit != 0);
         if constexpr (N >= kWave) {
-            if (c.lane == 0)
+            if (lane == 0)
                 *(uint64_t *)(ob + j0 / 8) = mask;
         } else {
-            if (c.lane < N / 8)
-                ob[c.lane] = (uint8_t)(mask >> (8 * c.lane));
+            if (lane < N / 8)
+                ob[lane] = (uint8_t)(mask >> (8 * lane));
         }
     }
-    if (opm && c.lane == 0)
-        *opm = fb.best;
+    if (opm && lane == 0)
+        *opm = best;
+}
+
+template <int M, int R, int L, int D>
+__device__ __forceinline__ void emit_codeword(const KernelArgs &args, const uint32_t *maps, FrameBest fb, uint8_t *ob,
+                                              float *opm, unsigned char *slice, int lane)
+{
+    const Ctx<M, R, L, D> c = frame_ctx<M, R, L, D>(args, slice, lane);
+    emit_masks<M, R, L, D>(maps + (size_t)fb.bestmap * kMapWords, fb.best, c.xbest(), ob, opm, lane);
     wave_sync();
 }
 
@@ -1411,6 +1420,98 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
         uint32_t tid; // opaque per frame: see rm_mixed_kernel
         asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"(threadIdx.x));
         decode_batch_frame<M, R, L, D>(args, f, rm_smem + (tid / kWave) * Sh::BYTES, (int)(tid & (kWave - 1)));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Frame-packed kernel for one decoder per frame (P = 1): the D decoder slots
+// of a wave decode D consecutive frames, one each, instead of one frame with
+// D - 1 idle slots.  Slot 0 keeps the slice's own copy of y; the copies of
+// slots 1 .. D-1 and the D winners' codeword masks follow the slice.
+// ---------------------------------------------------------------------------
+template <int M, int R, int L, int D>
+struct Packed {
+    using S = Shape<M, R, L, D>;
+    static constexpr int O_YX = S::BYTES;                  // y of slots 1 .. D-1, 4N bytes each
+    static constexpr int O_XB = O_YX + 4 * S::N * (D - 1); // [D][2G] winner masks
+    static constexpr int BYTES = ((O_XB + 16 * S::G * D + 4 * S::N - 1) / (4 * S::N)) * (4 * S::N);
+    __host__ __device__ static constexpr uint32_t yoff(uint32_t ds) { return ds == 0 ? 0u : O_YX + 4u * S::N * (ds - 1); }
+};
+
+// frames f0 .. f0+D-1 (those below n_frames) of a contiguous batch
+template <int M, int R, int L, int D>
+__device__ __forceinline__ void decode_packed(const KernelArgs &args, int64_t f0, unsigned char *slice, int lane)
+{
+    using Sh = Shape<M, R, L, D>;
+    using Pk = Packed<M, R, L, D>;
+    constexpr int N = Sh::N;
+    constexpr int G = Sh::G;
+    const int64_t left = args.n_frames - f0;
+    const int nf = left < D ? (int)left : D;
+    wave_sync();
+    // each slot's frame and its decoder's maps (slots past the last frame
+    // repeat frame f0; their results are not written)
+#pragma unroll
+    for (int t = 0; t < D; t++) {
+        const int64_t f = f0 + (t < nf ? t : 0);
+        const float *src = args.llr + f * N;
+        float *dst = (float *)(slice + Sh::O_Y + Pk::yoff((uint32_t)t));
+        for (int i = lane; i < N; i += kWave)
+            dst[i] = src[i];
+        const uint4 *mg = (const uint4 *)(args.maps + f * args.frame_stride);
+        uint4 *ml = (uint4 *)(slice + Sh::O_MAPS) + t * Sh::MAPS_PER_DEC * (kMapWords / 4);
+        for (int i = lane; i < args.maps_per_dec * (kMapWords / 4); i += kWave)
+            ml[i] = mg[i];
+    }
+    wave_sync();
+    int dlane; // opaque copy of the lane id, as in decode_decoders
+    asm volatile("v_mov_b32 %0, %1" : "=v"(dlane) : "v"(lane));
+    Ctx<M, R, L, D> c = frame_ctx<M, R, L, D>(args, slice, dlane);
+    c.yoff = Pk::yoff((uint32_t)c.ds);
+    const RootRes<M, R, L, D> r = decode_root<M, R, L, D>(c);
+    // Alg. 5 with one decoder: the first minimum over the list; a frame
+    // whose metrics are all +inf keeps the all-zero codeword
+    float pmin = from_lane(r.pm, (c.ds * L) * G);
+    int lstar = 0;
+#pragma unroll
+    for (int q = 1; q < L; q++) {
+        const float o = from_lane(r.pm, (c.ds * L + q) * G);
+        if (o < pmin) {
+            pmin = o;
+            lstar = q;
+        }
+    }
+    const bool found = pmin < __builtin_inff();
+    const int invmap = from_lane(r.invmap, (c.ds * L + lstar) * G);
+    uint64_t *xb = (uint64_t *)(slice + Pk::O_XB) + c.ds * 2 * G;
+    if (c.g == lstar) {
+        xb[c.lg] = found ? r.xlo : 0ull;
+        xb[G + c.lg] = found ? r.xhi : 0ull;
+    }
+    wave_sync();
+    for (int t = 0; t < nf; t++) {
+        const int64_t f = f0 + t;
+        const int bm = __builtin_amdgcn_readlane(invmap, t * L * G);
+        const float best = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pmin), t * L * G));
+        // (a frame without a finite metric has all-zero masks, which every map keeps all-zero)
+        const uint32_t *mi = args.maps + f * args.frame_stride + (size_t)bm * kMapWords;
+        emit_masks<M, R, L, D>(mi, best, (const uint64_t *)(slice + Pk::O_XB) + t * 2 * G,
+                               args.out_bits + f * (N / 8), args.out_pm ? args.out_pm + f : nullptr, lane);
+    }
+    wave_sync();
+}
+
+template <int M, int R, int L, int D, int WPE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) rm_decode_packed_kernel(KernelArgs args)
+{
+    using Pk = Packed<M, R, L, D>;
+    const int wave = (int)(threadIdx.x / kWave);
+    const int64_t groups = (args.n_frames + D - 1) / D;
+    const int64_t stride = (int64_t)gridDim.x * args.waves;
+    for (int64_t gi = xcd_block(blockIdx.x, gridDim.x) * args.waves + wave; gi < groups; gi += stride) {
+        uint32_t tid; // opaque per frame group: see rm_mixed_kernel
+        asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"(threadIdx.x));
+        decode_packed<M, R, L, D>(args, gi * D, rm_smem + (tid / kWave) * Pk::BYTES, (int)(tid & (kWave - 1)));
     }
 }
 

@@ -237,8 +237,7 @@ int fresh_decode(rm_decoder *d, const float *llr, int64_t n_frames, uint8_t *out
             KernelArgs a = batch_args(d, llr + f0 * d->N, nf, out_bits + f0 * (d->N / 8),
                                       out_metric ? out_metric + f0 : nullptr);
             a.frame_stride = per_frame;
-            const int blocks = (int)((nf + a.waves - 1) / a.waves);
-            e = d->kern->launch(a, blocks, d->stream);
+            e = launch_decoder(d, a, nf);
         }
         if (e == hipSuccess) {
             e = hipEventRecord(d->fresh_done, d->stream);

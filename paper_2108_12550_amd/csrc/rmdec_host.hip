@@ -54,6 +54,14 @@ KernelArgs batch_args(const rm_decoder *d, const float *llr, int64_t n_frames, u
     a.waves = d->cfg.waves_per_block;
     return a;
 }
+
+hipError_t launch_decoder(const rm_decoder *d, const KernelArgs &a, int64_t n_frames)
+{
+    const int64_t per_block = (int64_t)a.waves * (d->packed ? d->kern->D : 1);
+    const int64_t b = (n_frames + per_block - 1) / per_block;
+    const int blocks = (int)(b > (1 << 30) ? (1 << 30) : b);
+    return (d->packed ? d->kern->launch_packed : d->kern->launch)(a, blocks, d->stream);
+}
 } // namespace rmdec
 
 namespace {
@@ -423,6 +431,9 @@ rm_decoder *rm_decoder_create_ex(const rm_config *cfg)
     dec->nperm = d.nperm;
     dec->maps_per_dec = mpd;
     dec->kern = k;
+    // one decoder per frame: D frames per wave where a packed kernel exists
+    dec->packed = P == 1 && k->launch_packed != nullptr;
+    dec->slice_bytes = dec->packed ? k->lds_bytes_packed : k->lds_bytes_per_wave;
     dec->stream = nullptr;
     dec->table_bytes = host.size() * sizeof(uint32_t);
     dec->fresh_chunk = 0;
@@ -459,14 +470,14 @@ rm_decoder *rm_decoder_create_ex(const rm_config *cfg)
             // +12%, RM(2,9) P=20 L=4 +2.5% on MI355X), else as many waves as
             // 64 KiB of slices hold, up to 4 (RM(2,10) and RM(3,8) at L=8,
             // with 12 KiB slices, measured 1-3% slower with one)
-            if (k->lds_bytes_per_wave <= 8192) {
+            if (dec->slice_bytes <= 8192) {
                 wpb = 1;
             } else {
-                wpb = 65536 / k->lds_bytes_per_wave;
+                wpb = 65536 / dec->slice_bytes;
                 wpb = wpb < 1 ? 1 : (wpb > 4 ? 4 : wpb);
             }
         }
-        if ((size_t)wpb * k->lds_bytes_per_wave > 65536) {
+        if ((size_t)wpb * dec->slice_bytes > 65536) {
             delete dec;
             fail(RM_E_UNSUPPORTED, "LDS slice does not fit the requested waves per block");
             return nullptr;
@@ -535,7 +546,7 @@ int rm_decoder_info(const rm_decoder *d, rm_info *out)
     out->maps_per_decoder = d->maps_per_dec;
     out->waves_per_block = d->cfg.waves_per_block;
     out->lds_bytes_per_wave =
-        (size_t)(d->kern->block_lds_bytes > 0 ? d->kern->block_lds_bytes : d->kern->lds_bytes_per_wave);
+        (size_t)(d->kern->block_lds_bytes > 0 ? d->kern->block_lds_bytes : d->slice_bytes);
     out->table_bytes = d->table_bytes;
     return RM_OK;
 }
@@ -560,9 +571,7 @@ int rm_decode_batch(rm_decoder *d, const float *llr, int64_t n_frames, uint8_t *
     if (d->cfg.perm_mode == RM_PERM_FRESH)
         return fresh_decode(d, llr, n_frames, out_bits, out_metric);
     KernelArgs a = batch_args(d, llr, n_frames, out_bits, out_metric);
-    const int64_t blocks64 = (n_frames + a.waves - 1) / a.waves;
-    const int blocks = (int)(blocks64 > (1 << 30) ? (1 << 30) : blocks64);
-    hipError_t e = d->kern->launch(a, blocks, d->stream);
+    hipError_t e = launch_decoder(d, a, n_frames);
     if (e != hipSuccess)
         return fail(RM_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
     return RM_OK;

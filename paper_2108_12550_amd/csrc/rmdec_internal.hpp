@@ -12,6 +12,8 @@ struct rm_decoder {
     rm_config cfg;
     int N, K, nperm, maps_per_dec;
     const rmdec::KernelEntry *kern;
+    bool packed;     // P = 1 with a frame-packed kernel: D frames per wave
+    int slice_bytes; // LDS bytes per wave of the kernel that runs
     uint32_t *d_maps;   // the map tables (fresh mode: one chunk of frames' tables)
     size_t table_bytes;
     int64_t fresh_chunk; // fresh mode: frames whose tables the buffer holds
@@ -29,6 +31,8 @@ extern thread_local std::string g_err;
 int fail(int code, const std::string &msg);
 int check_device_ptr(const void *p, const char *name);
 KernelArgs batch_args(const rm_decoder *d, const float *llr, int64_t n_frames, uint8_t *out_bits, float *out_metric);
+// launch the decoder's batched kernel over n_frames frames (args from batch_args)
+hipError_t launch_decoder(const rm_decoder *d, const KernelArgs &a, int64_t n_frames);
 // fresh mode: draw each chunk's tables on the device, then decode the chunk
 int fresh_decode(rm_decoder *d, const float *llr, int64_t n_frames, uint8_t *out_bits, float *out_metric);
 } // namespace rmdec

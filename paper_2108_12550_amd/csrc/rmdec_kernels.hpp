@@ -19,6 +19,10 @@ struct KernelEntry {
     // kernels that run one workgroup per frame (lists of 16 or more paths):
     // the workgroup's LDS bytes; 0 for the one-wave-per-frame kernels
     int block_lds_bytes = 0;
+    // frame-packed kernel for P = 1 (D frames per wave, one per decoder
+    // slot) and its LDS bytes per wave; null where D = 1
+    LaunchFn launch_packed = nullptr;
+    int lds_bytes_packed = 0;
 };
 
 template <int M, int R, int L, int D, int WPE>
@@ -29,14 +33,23 @@ hipError_t launch_decode(const KernelArgs &args, int blocks, hipStream_t stream)
     return hipGetLastError();
 }
 
+template <int M, int R, int L, int D, int WPE>
+hipError_t launch_packed(const KernelArgs &args, int blocks, hipStream_t stream)
+{
+    const size_t lds = (size_t)args.waves * Packed<M, R, L, D>::BYTES;
+    hipLaunchKernelGGL((rm_decode_packed_kernel<M, R, L, D, WPE>), dim3(blocks), dim3(kWave * args.waves), lds, stream,
+                       args);
+    return hipGetLastError();
+}
+
 // Decoders per wavefront: D*L = 8 paths share the 64 lanes (8 lanes per
 // path); for N <= 256 at L = 4, 16 paths (4 lanes per path: per-node fixed
 // costs are shared by twice the decoders); for N = 1024 only 4 paths (16
 // lanes per path), which keeps a half-length node vector at 32 registers.
 // WPE: wavefronts per SIMD the register allocation must allow (4: at most
 // 128 VGPRs; 3: 168; 2: 256).  These choices keep every kernel free of (or
-// nearly free of) register spills; RM(2,9) at L = 4 runs 11% faster at four
-// waves per SIMD despite spilling six VGPRs.
+// nearly free of) register spills; RM(2,9) at L = 4 holds 123 VGPRs under
+// the cap of four waves per SIMD and spills nothing.
 constexpr int decoders_per_wave(int M, int L)
 {
     return L >= 8 ? 1 : (M >= 10 ? 4 : (M <= 8 && L == 4) ? 16 : 8) / L;
@@ -49,8 +62,13 @@ constexpr int waves_per_eu(int M, int R, int L)
 template <int M, int R, int L, int D = decoders_per_wave(M, L), int WPE = waves_per_eu(M, R, L)>
 constexpr KernelEntry entry()
 {
-    return KernelEntry{M, R, L, D, Shape<M, R, L, D>::BYTES, Shape<M, R, L, D>::MAPS_PER_DEC,
-                       &launch_decode<M, R, L, D, WPE>};
+    if constexpr (D > 1)
+        return KernelEntry{M, R, L, D, Shape<M, R, L, D>::BYTES, Shape<M, R, L, D>::MAPS_PER_DEC,
+                           &launch_decode<M, R, L, D, WPE>, 0, &launch_packed<M, R, L, D, WPE>,
+                           Packed<M, R, L, D>::BYTES};
+    else
+        return KernelEntry{M, R, L, D, Shape<M, R, L, D>::BYTES, Shape<M, R, L, D>::MAPS_PER_DEC,
+                           &launch_decode<M, R, L, D, WPE>};
 }
 
 // Each translation unit rmdec_inst_*.hip defines one table.

@@ -133,6 +133,35 @@ def test_plain_mode_other_codes():
         check(m, r, 1, 1, NONE, llr)
 
 
+# --- one decoder per frame (P = 1): the frame-packed kernel runs D frames
+# per wave, one per decoder slot; counts leave a ragged last group ---
+
+@pytest.mark.parametrize("m,r,L,mode,n", [
+    (7, 2, 1, NONE, 8 * 37 + 5),   # the plain FHT-FSC decoder of RM(2,7): 8 frames per wave
+    (9, 2, 1, PFHT, 8 * 13 + 7),
+    (9, 2, 4, PFHT, 2 * 41 + 1),   # p-FHT-FSCL-4 (M = 1): 2 frames per wave
+    (7, 2, 4, PFHT, 4 * 11 + 3),   # 4 frames per wave
+    (8, 3, 2, PFHT, 4 * 20 + 3),   # two permutation-domain nodes
+    (6, 1, 4, NONE, 4 * 9 + 2),    # first-order root
+    (5, 4, 4, PFHT, 4 * 9 + 1),    # SPC root
+    (9, 2, 4, NONE, 2 * 30 + 1),
+])
+def test_single_decoder_packed(m, r, L, mode, n):
+    _, llr = synth.frames(m, r, n, 2.5, seed=600 + 10 * m + L)
+    check(m, r, 1, L, mode, llr)
+
+
+@pytest.mark.parametrize("waves", [1, 2, 4])
+def test_single_decoder_packed_tile_invariance(waves):
+    _, llr = synth.frames(7, 2, 301, 2.0, seed=610)
+    ref = gpu_decode(7, 2, 1, 1, 0, NONE, llr, waves=0)
+    got = gpu_decode(7, 2, 1, 1, 0, NONE, llr, waves=waves)
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+    for k in (0, 7, 8, 300):  # alone: a group of one frame
+        one = gpu_decode(7, 2, 1, 1, 0, NONE, llr[k:k + 1], waves=waves)
+        assert np.array_equal(one[0][0], ref[0][k]) and one[1][0] == ref[1][k]
+
+
 # --- ties: integer-valued and all-zero LLRs exercise every tie-break rule ---
 
 @pytest.mark.parametrize("m,r,P,L", [(5, 2, 2, 4), (7, 2, 3, 4), (8, 3, 2, 8), (9, 2, 4, 4), (6, 3, 2, 2),
