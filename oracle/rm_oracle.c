@@ -267,9 +267,59 @@ static void stable_sort_desc(int *ord, const float *key, int n)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Alg. 4: FHT decoding of one path of a first-order node RM(1,s), with the  */
-/* low-cost path metric of Eq. (10).  Returns k = min(L, 2^s) candidates:    */
-/* codewords cw[j*n..], metrics pm[j] and the transform index idx[j].        */
+/* Walsh-Hadamard transform by the Plotkin split (Section II-C): the halves  */
+/* lo = F[0..n/2), hi = F[n/2..n) become (hi - lo, hi + lo), then each half  */
+/* is transformed on its own.  F[i] ends as the correlation of alpha with    */
+/* the +-1 image of the first-order codeword that index i stands for.        */
+/* ------------------------------------------------------------------------ */
+static void hadamard(float *F, int n)
+{
+    if (n < 2)
+        return;
+    const int h = n / 2;
+    for (int i = 0; i < h; i++) {
+        const float lo = F[i], hi = F[i + h];
+        F[i] = hi - lo;
+        F[i + h] = hi + lo;
+    }
+    hadamard(F, h);
+    hadamard(F + h, h);
+}
+
+/* The k largest of key[0..n) as indices, largest first, ties to the lower */
+/* index: k scans, each taking the largest entry not yet taken.             */
+static void largest_k(const float *key, int n, int k, int *out)
+{
+    uint8_t *taken = calloc((size_t)n, 1);
+    for (int j = 0; j < k; j++) {
+        int best = -1;
+        for (int i = 0; i < n; i++)
+            if (!taken[i] && (best < 0 || key[i] > key[best]))
+                best = i;
+        taken[best] = 1;
+        out[j] = best;
+    }
+    free(taken);
+}
+
+/* Message word of the first-order codeword selected by transform index i   */
+/* and the sign of F[i] (Section II-C, Alg. 4): the sign gives the constant */
+/* term m_s; the s linear terms are the binary digits of 2^s - 1 - i, the   */
+/* least significant digit first (m_t = bit s-1-t).                          */
+static void first_order_message(int s, int i, int negative, uint8_t *msg)
+{
+    const unsigned c = (unsigned)((1 << s) - 1 - i);
+    for (int t = 0; t < s; t++)
+        msg[t] = (uint8_t)((c >> (s - 1 - t)) & 1u);
+    msg[s] = (uint8_t)negative;
+}
+
+/* ------------------------------------------------------------------------ */
+/* FHT decoding of one path at a first-order node RM(1,s) (Alg. 4), with   */
+/* the metric of Eq. (10).  The k = min(L, 2^s) candidates are the indices  */
+/* of the k largest |F| (ties to the lower index); each gives a codeword    */
+/* (its message through G^{(x)s}) and the metric pm_in + (sum|alpha| -      */
+/* |F[i]|) / 2.  Writes cw[j*n..], pm[j], idx[j] for j < k; returns k.      */
 /* ------------------------------------------------------------------------ */
 int rmo_fht(int s, int L, const float *alpha, float pm_in, uint8_t *cw, float *pm, int *idx)
 {
@@ -278,64 +328,39 @@ int rmo_fht(int s, int L, const float *alpha, float pm_in, uint8_t *cw, float *p
     const int n = 1 << s;
     const int k = L < n ? L : n;
     float *F = malloc((size_t)n * sizeof *F);
-    float *ab = malloc((size_t)n * sizeof *ab);
-    uint8_t *taken = calloc((size_t)n, 1);
+    float *mag = malloc((size_t)n * sizeof *mag);
+    int *ord = malloc((size_t)n * sizeof *ord);
     uint8_t *info = malloc((size_t)n);
     uint8_t *u = malloc((size_t)n);
     rmo_info_set(s, 1, info);
 
-    /* Initialisation: working copy and LLR_abs = sum of |alpha|. */
-    for (int i = 0; i < n; i++) {
-        F[i] = alpha[i];
-        ab[i] = fabsf(alpha[i]);
-    }
-    const float llr_abs = tree_sum(ab, n);
+    for (int i = 0; i < n; i++)
+        mag[i] = fabsf(alpha[i]);
+    const float sum_abs = tree_sum(mag, n);
 
-    /* In-place butterflies, stride 2^{s-t-1} for t = 0..s-1; 2^t blocks of
-     * width 2^{s-t} (the block loop bound of the listing is read as j < 2^t). */
-    for (int t = 0; t < s; t++) {
-        const int h = 1 << (s - t - 1);
-        for (int j = 0; j < (1 << t); j++)
-            for (int i = j * 2 * h; i < j * 2 * h + h; i++) {
-                const float a = F[i + h] - F[i];
-                const float b = F[i + h] + F[i];
-                F[i] = a;
-                F[i + h] = b;
-            }
-    }
+    memcpy(F, alpha, (size_t)n * sizeof *F);
+    hadamard(F, n);
 
-    /* Up to L best entries of |F|: L passes that each take the largest entry
-     * not yet taken (ties go to the lower index), as the text describes. */
-    for (int j = 0; j < k; j++) {
-        int best = -1;
-        for (int i = 0; i < n; i++)
-            if (!taken[i] && (best < 0 || fabsf(F[i]) > fabsf(F[best])))
-                best = i;
-        taken[best] = 1;
-        idx[j] = best;
-    }
+    for (int i = 0; i < n; i++)
+        mag[i] = fabsf(F[i]);
+    largest_k(mag, n, k, ord); /* largest |F| first, ties to the lower index */
 
     for (int j = 0; j < k; j++) {
-        const int is = idx[j];
+        const int i = ord[j];
         uint8_t msg[MAXM + 1];
-        msg[s] = (uint8_t)(F[is] < 0.0f);          /* m_s from the sign */
-        const unsigned c = (unsigned)(n - 1 - is); /* dec2bin(2^s - 1 - i*) */
-        /* {m_{s-1}, ..., m_0} lists the binary digits of c least significant
-         * first, i.e. m_t is bit s-1-t of c. */
-        for (int t = 0; t < s; t++)
-            msg[t] = (uint8_t)((c >> (s - 1 - t)) & 1u);
+        first_order_message(s, i, F[i] < 0.0f, msg);
+        /* information positions of RM(1,s) in increasing order: the s rows
+         * of weight 2^(s-1) carry m_0 .. m_(s-1), the all-ones row m_s */
         int t = 0;
-        for (int kk = 0; kk < n; kk++) {
-            u[kk] = 0;
-            if (info[kk])
-                u[kk] = msg[t++];
-        }
+        for (int q = 0; q < n; q++)
+            u[q] = info[q] ? msg[t++] : 0;
         rmo_encode(s, u, cw + (size_t)j * n);
-        pm[j] = pm_in + 0.5f * (llr_abs - fabsf(F[is]));
+        idx[j] = i;
+        pm[j] = pm_in + 0.5f * (sum_abs - mag[i]);
     }
     free(F);
-    free(ab);
-    free(taken);
+    free(mag);
+    free(ord);
     free(info);
     free(u);
     return k;
@@ -713,8 +738,7 @@ int rmo_schedule(int m, int r, int perm_mode, int *out, int cap)
 /* Alg. 2: p-FHT-FSCL on node RM(r,m) with L paths.                          */
 /* In:  alpha[l] (n = 2^m LLRs), pm_in[l].                                    */
 /* Out: x[l] (n bits as bytes), pm_out[l], anc[l] = input path from which    */
-/*      output path l descends (the index written l_org in the listing when  */
-/*      it refers to the surviving ancestor).                                 */
+/*      output path l descends (the surviving ancestor).                      */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     const rmo_decoder *dec;

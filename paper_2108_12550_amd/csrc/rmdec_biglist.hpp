@@ -76,6 +76,35 @@ struct Lay {
 
     static constexpr int a_off(int s) { return A + L * ((1 << s) - 2); }
     static constexpr int xb_off(int s, int side) { return XB + xb_below(s) + side * L * words_of(s); }
+
+    // Every array the kernel indexes ends at or before the next one begins,
+    // for the largest index its accessors form (row l < L, element i < 2^s,
+    // level s, side, permutation-domain depth v < kMaxPerm), and the 8-byte
+    // accesses of the SPC flip masks are aligned.  Checked for every built
+    // shape when the kernel is instantiated.
+    static constexpr bool layout_ok()
+    {
+        if (L % 4 != 0 || L > 256 || M < 4)
+            return false;
+        for (int s = 1; s < M; s++) // level rows: a_off(s) + l 2^s + i
+            if (a_off(s) < A || a_off(s) + L * (1 << s) > A_END)
+                return false;
+        for (int s = 3; s < M; s++) // both children's codeword bits of level s
+            if (xb_off(s, 1) + L * words_of(s) > xb_off(s + 1, 0))
+                return false;
+        if (XB < A_END || xb_off(3, 0) != XB || xb_off(M, 0) + L * words_of(M) > XB_END)
+            return false;
+        return PM >= XB_END && PM + (M - 2) * 2 * L <= ANC            // [M-2][2][L] floats
+               && ANC + (M - 2) * 2 * L / 4 <= SEL                     // [M-2][2][L] bytes
+               && SEL + kMaxPerm * 2 * L / 4 <= ORIG                   // [kMaxPerm][2L] bytes
+               && ORIG + kMaxPerm * L / 4 <= PPM                       // [kMaxPerm][L] bytes
+               && PPM + kMaxPerm * L <= SCR                            // [kMaxPerm][L] floats
+               && SCR + 2 * L <= PM0 && PM0 + L <= SIDX                // 2L and L floats
+               && SIDX + L / 2 <= PAR && PAR + L / 4 <= SPC            // L uint16, L bytes
+               && SPC % 2 == 0 && SPC_ONE % 2 == 0 && (3 * L) % 2 == 0 // flip masks: 8-byte aligned
+               && SPC + 2 * SPC_ONE <= BEST                            // two copies of 5L words
+               && BEST + (N / 32 > 0 ? N / 32 : 1) <= MISC && MISC + 4 <= WORDS;
+    }
 };
 
 template <int S>
@@ -200,6 +229,7 @@ __device__ __forceinline__ void wave_umin2(uint64_t v1, uint64_t v2, uint64_t &m
 template <int M, int L>
 struct BigCtx {
     using Ly = Lay<M, L>;
+    static_assert(Ly::layout_ok(), "large-list LDS arrays overlap or leave the slice");
     uint32_t *w;            // LDS words
     const uint32_t *dmaps;  // this decoder's maps
     int tid;

@@ -344,6 +344,7 @@ struct Ctx {
     using S = Shape<M, R, L, D>;
     unsigned char *base;
     uint32_t yoff; // byte offset of this decoder's channel LLRs from O_Y (frame-packed kernels)
+    uint32_t moff; // word offset of this decoder's maps from O_MAPS
     int lane, lg;
     int g;  // path within the decoder
     int gb; // first group of this lane's decoder
@@ -355,7 +356,7 @@ struct Ctx {
     __device__ uint32_t y_addr() const { return lds_addr(base) + S::O_Y + yoff; }
     __device__ uint32_t stage_addr() const { return lds_addr(base) + S::O_STAGE; }
     __device__ uint32_t *maps_all() const { return (uint32_t *)(base + S::O_MAPS); }
-    __device__ uint32_t *maps() const { return maps_all() + ds * S::MAPS_PER_DEC * kMapWords; }
+    __device__ uint32_t *maps() const { return maps_all() + moff; }
     __device__ float *stage() const { return (float *)(base + S::O_STAGE); }
     __device__ float *cpm_all() const { return (float *)(base + S::O_CPM); }
     __device__ float *cpm() const { return cpm_all() + ds * L * L; }
@@ -1255,6 +1256,7 @@ __device__ __forceinline__ Ctx<M, R, L, D> frame_ctx(const KernelArgs &args, uns
     c.g = (int)(gw % L);
     c.gb = (int)(gw - gw % L);
     c.ds = (int)(gw / L);
+    c.moff = (uint32_t)c.ds * (Sh::MAPS_PER_DEC * kMapWords);
     c.lg = (int)(ul % G);
     c.pfht = args.pfht;
     return c;
@@ -1338,13 +1340,20 @@ __device__ __forceinline__ void emit_masks(const uint32_t *mi, float best, const
     for (int k = 0; k < M; k++)
         col[k] = mi[k] >> 2;
     col[M] = mi[kMapB] >> 2;
+    // image of position j = j0 + lane: the lane's bits folded once, the bits
+    // of j0 (a multiple of 64, known at compile time) per block
+    uint32_t el = col[M];
+#pragma unroll
+    for (int k = 0; k < M && k < 6; k++)
+        el ^= (((uint32_t)lane >> k) & 1u) ? col[k] : 0u;
 #pragma unroll
     for (int j0 = 0; j0 < N; j0 += kWave) {
         const uint32_t j = (uint32_t)(j0 + lane);
-        uint32_t e = col[M];
+        uint32_t eh = 0;
 #pragma unroll
-        for (int k = 0; k < M; k++)
-            e ^= ((j >> k) & 1u) ? col[k] : 0u;
+        for (int k = 6; k < M; k++)
+            eh ^= ((j0 >> k) & 1) ? col[k] : 0u;
+        uint32_t e = el ^ eh;
         uint32_t bit = 0;
         if (j < (uint32_t)N) {
             e &= (uint32_t)(N - 1);
@@ -1449,16 +1458,24 @@ __device__ __forceinline__ void decode_packed(const KernelArgs &args, int64_t f0
     const int64_t left = args.n_frames - f0;
     const int nf = left < D ? (int)left : D;
     wave_sync();
-    // each slot's frame and its decoder's maps (slots past the last frame
-    // repeat frame f0; their results are not written)
+    // each slot's frame (16-byte moves; slots past the last frame repeat
+    // frame f0 and their results are not written)
+    constexpr int QF = N / 4; // 16-byte words per frame
 #pragma unroll
-    for (int t = 0; t < D; t++) {
-        const int64_t f = f0 + (t < nf ? t : 0);
-        const float *src = args.llr + f * N;
-        float *dst = (float *)(slice + Sh::O_Y + Pk::yoff((uint32_t)t));
-        for (int i = lane; i < N; i += kWave)
-            dst[i] = src[i];
-        const uint4 *mg = (const uint4 *)(args.maps + f * args.frame_stride);
+    for (int q0 = 0; q0 < D * QF; q0 += kWave) {
+        const int q = q0 + lane;
+        if (D * QF % kWave == 0 || q < D * QF) {
+            const int t = q / QF;
+            const int64_t f = f0 + (t < nf ? t : 0);
+            const uint4 v = ((const uint4 *)(args.llr + f * N))[q % QF];
+            *(uint4 *)(slice + Sh::O_Y + Pk::yoff((uint32_t)t) + 16 * (q % QF)) = v;
+        }
+    }
+    // the decoder's maps: one copy shared by all slots when every frame
+    // uses the same tables, else each slot's frame's own
+    const int nmap = args.frame_stride == 0 ? 1 : D;
+    for (int t = 0; t < nmap; t++) {
+        const uint4 *mg = (const uint4 *)(args.maps + (f0 + (t < nf ? t : 0)) * args.frame_stride);
         uint4 *ml = (uint4 *)(slice + Sh::O_MAPS) + t * Sh::MAPS_PER_DEC * (kMapWords / 4);
         for (int i = lane; i < args.maps_per_dec * (kMapWords / 4); i += kWave)
             ml[i] = mg[i];
@@ -1468,6 +1485,8 @@ __device__ __forceinline__ void decode_packed(const KernelArgs &args, int64_t f0
     asm volatile("v_mov_b32 %0, %1" : "=v"(dlane) : "v"(lane));
     Ctx<M, R, L, D> c = frame_ctx<M, R, L, D>(args, slice, dlane);
     c.yoff = Pk::yoff((uint32_t)c.ds);
+    if (args.frame_stride == 0)
+        c.moff = 0;
     const RootRes<M, R, L, D> r = decode_root<M, R, L, D>(c);
     // Alg. 5 with one decoder: the first minimum over the list; a frame
     // whose metrics are all +inf keeps the all-zero codeword
@@ -1493,8 +1512,10 @@ __device__ __forceinline__ void decode_packed(const KernelArgs &args, int64_t f0
         const int64_t f = f0 + t;
         const int bm = __builtin_amdgcn_readlane(invmap, t * L * G);
         const float best = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pmin), t * L * G));
-        // (a frame without a finite metric has all-zero masks, which every map keeps all-zero)
-        const uint32_t *mi = args.maps + f * args.frame_stride + (size_t)bm * kMapWords;
+        // the winner's inverse map, from the slot's copy in LDS (a frame
+        // without a finite metric has all-zero masks, which every map keeps all-zero)
+        const uint32_t *mi = (const uint32_t *)(slice + Sh::O_MAPS) +
+                             (args.frame_stride == 0 ? 0 : t * Sh::MAPS_PER_DEC * kMapWords) + bm * kMapWords;
         emit_masks<M, R, L, D>(mi, best, (const uint64_t *)(slice + Pk::O_XB) + t * 2 * G,
                                args.out_bits + f * (N / 8), args.out_pm ? args.out_pm + f : nullptr, lane);
     }
