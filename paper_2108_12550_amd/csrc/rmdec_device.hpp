@@ -1641,16 +1641,31 @@ struct ServeArgs {
     uint32_t *head; // next tile to take; zero when the step starts
     uint8_t *out_bits;
     float *out_pm;
+    uint32_t *done; // per output slot: set to `epoch` once its codeword and metric are written
+    uint32_t epoch;
 };
+
+// A request's outputs are complete: after the wave's writes to them (all by
+// lane 0) are visible system-wide, its completion word takes the step's
+// epoch, so that a host thread polling the word may read the outputs.
+__device__ __forceinline__ void signal_done(const ServeArgs &a, uint32_t slot, int lane)
+{
+    if (lane == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+        __hip_atomic_store(a.done + slot, a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
 
 template <class C>
 __device__ __forceinline__ void serve_tile(const ServeArgs &a, const KernelArgs &ka, const Tile &t, unsigned char *slice,
                                            int lane)
 {
+    static_assert(C::Sh::N >= kWave, "signal_done orders lane 0's writes: every output word must come from lane 0");
     for (uint32_t k = 0; k < t.count; k++) {
         const Job j = a.jobs[t.first + k];
         decode_frame<C::M, C::R, C::L, C::D>(ka, ka.maps, j.llr, a.out_bits + (size_t)j.out * kServeBitsStride, a.out_pm + j.out,
                                              slice, lane);
+        signal_done(a, j.out, lane);
     }
 }
 
@@ -1737,6 +1752,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
                                    0)
                                 : 0),
                  ...);
+                signal_done(a, j.out, lane);
             }
             __syncthreads();
         }

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <deque>
 #include <new>
@@ -59,13 +60,18 @@ struct Batch {
     hipEvent_t done = nullptr;
     unsigned char *h_tab = nullptr, *d_tab = nullptr; // heads | segs | codes | jobs | tiles
     unsigned char *h_llr = nullptr, *d_llr = nullptr;
-    unsigned char *h_out = nullptr, *d_out = nullptr; // bits [max_batch][128] | metrics [max_batch]
+    // outputs in coherent host memory that the kernels write directly:
+    // bits [max_batch][128] | metrics [max_batch] | completion words [max_batch]
+    unsigned char *h_out = nullptr, *d_out = nullptr; // host address, device address
+    uint32_t epoch = 0;       // value of the completion words of this launch
     int64_t llr_used = 0;
     std::vector<ReqMeta> reqs;
+    // requests not yet returned by poll, per serving kernel, in the order
+    // that kernel takes them
+    std::vector<int> unreported[kGroups];
     const rm_decoder *seg_dec[kMaxSegs];
     int n_segs = 0;
     double t_launch = 0, t_done = 0;
-    size_t harvested = 0;
 };
 
 } // namespace
@@ -75,7 +81,8 @@ struct rm_server {
     int device = 0;
     int waves = 2;                      // waves per block, one request per wave (split = 1)
     int grid_max[kGroups] = {0, 0, 0};  // resident blocks of each serving kernel
-    size_t off_segs = 0, off_codes = 0, off_jobs = 0, tab_bytes = 0, out_pm_off = 0;
+    size_t off_segs = 0, off_codes = 0, off_jobs = 0, tab_bytes = 0, out_pm_off = 0, out_done_off = 0;
+    uint32_t epochs = 0;        // launches so far (each launch's completion words take the next value)
     std::vector<Batch> batches;
     int open = -1;              // index of the open batch, or -1
     int inflight = 0;           // batches launched and not yet finished
@@ -104,14 +111,14 @@ void free_batch(Batch &b)
     for (unsigned char *p : {b.h_tab, b.h_llr, b.h_out})
         if (p)
             (void)hipHostFree(p);
-    for (unsigned char *p : {b.d_tab, b.d_llr, b.d_out})
+    for (unsigned char *p : {b.d_tab, b.d_llr})
         if (p)
             (void)hipFree(p);
 }
 
 hipError_t alloc_batch(rm_server *s, Batch &b)
 {
-    const size_t out_bytes = s->out_pm_off + (size_t)s->cfg.max_batch * 4;
+    const size_t out_bytes = s->out_done_off + (size_t)s->cfg.max_batch * 4;
     hipError_t e = hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking);
     for (int i = 0; i < 2 && e == hipSuccess; i++)
         e = hipStreamCreateWithFlags(&b.side[i], hipStreamNonBlocking);
@@ -122,14 +129,17 @@ hipError_t alloc_batch(rm_server *s, Batch &b)
         e = hipHostMalloc((void **)&b.h_tab, s->tab_bytes, hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipHostMalloc((void **)&b.h_llr, (size_t)s->cfg.batch_bytes, hipHostMallocDefault);
+    // coherent and mapped: the kernels' writes reach it while they run
     if (e == hipSuccess)
-        e = hipHostMalloc((void **)&b.h_out, out_bytes, hipHostMallocDefault);
+        e = hipHostMalloc((void **)&b.h_out, out_bytes, hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) {
+        memset(b.h_out, 0, out_bytes); // completion words start below every epoch
+        e = hipHostGetDevicePointer((void **)&b.d_out, b.h_out, 0);
+    }
     if (e == hipSuccess)
         e = hipMalloc((void **)&b.d_tab, s->tab_bytes);
     if (e == hipSuccess)
         e = hipMalloc((void **)&b.d_llr, (size_t)s->cfg.batch_bytes);
-    if (e == hipSuccess)
-        e = hipMalloc((void **)&b.d_out, out_bytes);
     b.reqs.reserve((size_t)s->cfg.max_batch);
     return e;
 }
@@ -145,8 +155,9 @@ bool open_batch(rm_server *s)
             b.state = Batch::OPEN;
             b.llr_used = 0;
             b.reqs.clear();
+            for (auto &u : b.unreported)
+                u.clear();
             b.n_segs = 0;
-            b.harvested = 0;
             s->open = (int)i;
             return true;
         }
@@ -193,6 +204,12 @@ int launch_open(rm_server *s)
         const ReqMeta &r = b.reqs[i];
         jobs[fill[r.seg]++] = Job{r.llr_dev, (uint32_t)i, 0u};
     }
+    // poll scans each kernel's requests in the order the kernel takes them
+    for (int k = 0; k < n; k++) {
+        const int i = (int)jobs[k].out;
+        b.unreported[group_of(b.seg_dec[b.reqs[(size_t)i].seg]->cfg.L)].push_back(i);
+    }
+    b.epoch = ++s->epochs == 0 ? ++s->epochs : s->epochs; // never 0, the words' initial value
     const int tf = s->cfg.tile_frames;
     int n_tiles = 0;
     int g_first[kGroups] = {0, 0, 0}, g_count[kGroups] = {0, 0, 0};
@@ -231,6 +248,8 @@ int launch_open(rm_server *s)
         a.head = (uint32_t *)b.d_tab + g;
         a.out_bits = b.d_out;
         a.out_pm = (float *)(b.d_out + s->out_pm_off);
+        a.done = (uint32_t *)(b.d_out + s->out_done_off);
+        a.epoch = b.epoch;
         if (s->cfg.split > 1) {
             // one queue entry per workgroup at a time, its requests split over the waves
             e = group(g).launch_split(a, std::min(g_count[g], s->grid_max[g]), s->cfg.split, st);
@@ -244,11 +263,6 @@ int launch_open(rm_server *s)
     for (int g = 1; e == hipSuccess && g < kGroups; g++)
         if (g_count[g])
             e = hipStreamWaitEvent(b.stream, b.side_done[g - 1], 0);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(b.h_out, b.d_out, (size_t)n * kServeBitsStride, hipMemcpyDeviceToHost, b.stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(b.h_out + s->out_pm_off, b.d_out + s->out_pm_off, (size_t)n * 4, hipMemcpyDeviceToHost,
-                           b.stream);
     if (e == hipSuccess)
         e = hipEventRecord(b.done, b.stream);
     if (e != hipSuccess)
@@ -326,6 +340,7 @@ rm_server *rm_server_create(const rm_server_config *cfg)
     s->off_jobs = align_up(s->off_codes + kMaxSegs * sizeof(int), 16);
     s->tab_bytes = s->off_jobs + (size_t)c.max_batch * (sizeof(Job) + sizeof(Tile));
     s->out_pm_off = (size_t)c.max_batch * kServeBitsStride;
+    s->out_done_off = s->out_pm_off + (size_t)c.max_batch * 4;
     hipError_t e = hipGetDevice(&s->device);
     int cus = 0;
     if (e == hipSuccess)
@@ -440,35 +455,61 @@ int rm_server_poll(rm_server *s, rm_completion *out, int max)
     int rc = retire(s);
     if (rc != RM_OK)
         return rc;
+    // Every request whose completion word holds its launch's epoch is done
+    // (the kernel wrote its outputs before the word); launched batches are
+    // scanned oldest first, each in the order its kernels take the requests.
+    // A kernel takes its queue entries in order, so once kMissRun requests in
+    // a row are not done the rest of that list is left for a later poll.
+    constexpr int kMissRun = 2048;
     int k = 0;
-    while (k < max && !s->order.empty()) {
-        Batch &b = s->batches[s->order.front()];
-        if (b.state != Batch::DONE)
-            break;
+    for (int bi : s->order) {
+        Batch &b = s->batches[bi];
+        const volatile uint32_t *done = (const volatile uint32_t *)(b.h_out + s->out_done_off);
         const float *pm = (const float *)(b.h_out + s->out_pm_off);
-        while (k < max && b.harvested < b.reqs.size()) {
-            const size_t i = b.harvested++;
-            const ReqMeta &r = b.reqs[i];
-            rm_completion &c = out[k++];
-            c.ticket = r.ticket;
-            c.tag = r.tag;
-            c.status = RM_OK;
-            c.n_bytes = r.n_bytes;
-            c.metric = pm[i];
-            memcpy(c.bits, b.h_out + i * kServeBitsStride, (size_t)r.n_bytes);
-            c.t_arrival_us = r.t_arrival;
-            c.t_launch_us = b.t_launch;
-            c.t_done_us = b.t_done;
-            if (r.out_bits)
-                memcpy(r.out_bits, c.bits, (size_t)r.n_bytes);
-            if (r.out_metric)
-                *r.out_metric = c.metric;
-            s->pending--;
+        const double t_seen = now_us();
+        for (std::vector<int> &un : b.unreported) {
+            size_t keep = 0;
+            int miss = 0;
+            for (size_t q = 0; q < un.size(); q++) {
+                const int i = un[q];
+                if (k == max || miss >= kMissRun || done[i] != b.epoch) {
+                    un[keep++] = i;
+                    miss++;
+                    continue;
+                }
+                miss = 0;
+                std::atomic_thread_fence(std::memory_order_acquire);
+                const ReqMeta &r = b.reqs[(size_t)i];
+                rm_completion &c = out[k++];
+                c.ticket = r.ticket;
+                c.tag = r.tag;
+                c.status = RM_OK;
+                c.n_bytes = r.n_bytes;
+                c.metric = pm[i];
+                memcpy(c.bits, b.h_out + (size_t)i * kServeBitsStride, (size_t)r.n_bytes);
+                c.t_arrival_us = r.t_arrival;
+                c.t_launch_us = b.t_launch;
+                c.t_done_us = t_seen;
+                if (r.out_bits)
+                    memcpy(r.out_bits, c.bits, (size_t)r.n_bytes);
+                if (r.out_metric)
+                    *r.out_metric = c.metric;
+                s->pending--;
+            }
+            un.resize(keep);
         }
-        if (b.harvested == b.reqs.size()) {
-            b.state = Batch::FREE;
-            s->order.pop_front();
-        }
+    }
+    // a batch is reused once all its requests are returned and its kernels
+    // have finished
+    while (!s->order.empty()) {
+        Batch &b = s->batches[s->order.front()];
+        bool all = true;
+        for (const auto &u : b.unreported)
+            all = all && u.empty();
+        if (b.state != Batch::DONE || !all)
+            break;
+        b.state = Batch::FREE;
+        s->order.pop_front();
     }
     rc = maybe_launch(s);
     return rc != RM_OK ? rc : k;

@@ -217,3 +217,41 @@ def test_unsupported_and_foreign_pointers():
     while srv.pending():
         srv.poll()
     srv.close()
+
+
+def test_requests_complete_individually():
+    """A request is returned as soon as its own outputs are written, not when
+    its batch ends: in one batch with a heavy request (RM(2,10), P = 32,
+    L = 8) and light ones (RM(2,7), P = 8, L = 1), the light requests are
+    returned before the heavy one, and every result is still that of
+    rm_decode_batch."""
+    heavy = rmd.Decoder(10, 2, 32, 8, seed=3)
+    light = rmd.Decoder(7, 2, 8, 1, seed=4)
+    _, yh = synth.frames(10, 2, 1, 2.5, seed=91)
+    _, yl = synth.frames(7, 2, 200, 2.5, seed=92)
+    th, tl = torch.from_numpy(yh).cuda(), torch.from_numpy(yl).cuda()
+    ref_h = [a.cpu().numpy() for a in heavy.decode(th)]
+    ref_l = [a.cpu().numpy() for a in light.decode(tl)]
+    torch.cuda.synchronize()
+    srv = rmd.Server(batch_bytes=8 << 20, max_batch=1024, depth=1)
+    srv.register_pool(th)
+    srv.register_pool(tl)
+    # the first request is launched alone; without a poll it stays in flight,
+    # so the following ones gather in the next batch
+    assert srv.submit(light, tl.data_ptr(), True, tag=1000) is not None
+    assert srv.submit(heavy, th.data_ptr(), True, tag=999) is not None
+    for i in range(200):
+        assert srv.submit(light, tl.data_ptr() + 512 * i, True, tag=i) is not None
+    done = {}
+    while len(done) < 202:
+        for ticket, tag, bits, metric, ta, tlch, td in srv.poll():
+            done[tag] = (bits, metric, td)
+    t_heavy = done[999][2]
+    t_light = np.array([done[i][2] for i in range(200)])
+    print(f"  heavy request done at {t_heavy - t_light.min():.0f} us after the first light one; "
+          f"light requests before it: {(t_light < t_heavy).sum()} of 200", flush=True)
+    assert (t_light < t_heavy).sum() >= 150
+    assert np.frombuffer(done[999][0], np.uint8).tobytes() == ref_h[0][0].tobytes() and done[999][1] == ref_h[1][0]
+    for i in range(200):
+        assert np.frombuffer(done[i][0], np.uint8).tobytes() == ref_l[0][i].tobytes() and done[i][1] == ref_l[1][i]
+    srv.close()
