@@ -873,6 +873,20 @@ __device__ __forceinline__ NodeRes<(1 << S), kWave / (L * D)> spcl(const Ctx<M, 
         hd |= (valid && A[j] < 0.0f) ? ((MaskT)1 << j) : (MaskT)0;
     const uint32_t par = bfly_xor<ACT / 2>((uint32_t)(__popcll((uint64_t)hd) & 1));
 
+    if constexpr (tau == 0 && n <= G) {
+        // Wagner decoding (no splits): the least reliable position o_0 is the
+        // group minimum of (|alpha|, index), one element per lane; its key
+        // also carries the element's hard decision.  Metric Eq. (3); the
+        // parity is restored at o_0 (Eq. (6)).
+        const uint64_t key = valid ? (((uint64_t)__float_as_uint(fabsf(A[0])) << 32) | ((uint32_t)lg << 1) | (uint32_t)hd)
+                                   : ~0ull;
+        const uint64_t mn = ~bfly_umax<ACT / 2>(~key);
+        const uint32_t o0 = ((uint32_t)mn >> 1) & 0xFFu;
+        const float cur0 = par ? pm + __uint_as_float((uint32_t)(mn >> 32)) : pm;
+        const MaskT x = (uint32_t)lg == o0 ? (MaskT)(par ^ ((uint32_t)mn & 1u)) : hd;
+        return {x, cur0, g};
+    }
+
     // o_0 .. o_tau: |alpha| ascending, ties to the lower index
     float *spca = c.spca();
     int *spci = c.spci();
@@ -1447,6 +1461,17 @@ struct Packed {
     __host__ __device__ static constexpr uint32_t yoff(uint32_t ds) { return ds == 0 ? 0u : O_YX + 4u * S::N * (ds - 1); }
 };
 
+// 8 x 8 bit transpose: bit 8b + l of the result is bit 8l + b of x
+__device__ __forceinline__ uint64_t transpose8x8(uint64_t x)
+{
+    uint64_t t = (x ^ (x >> 7)) & 0x00AA00AA00AA00AAull;
+    x = x ^ t ^ (t << 7);
+    t = (x ^ (x >> 14)) & 0x0000CCCC0000CCCCull;
+    x = x ^ t ^ (t << 14);
+    t = (x ^ (x >> 28)) & 0x00000000F0F0F0F0ull;
+    return x ^ t ^ (t << 28);
+}
+
 // frames f0 .. f0+D-1 (those below n_frames) of a contiguous batch
 template <int M, int R, int L, int D>
 __device__ __forceinline__ void decode_packed(const KernelArgs &args, int64_t f0, unsigned char *slice, int lane)
@@ -1501,6 +1526,36 @@ __device__ __forceinline__ void decode_packed(const KernelArgs &args, int64_t f0
         }
     }
     const bool found = pmin < __builtin_inff();
+    if constexpr (L == 1 && G == 8 && N >= 128) {
+        if (!args.pfht) {
+            // Plain mode: every map is the identity, so the codeword in
+            // channel order is the root's row layout read out directly.
+            // Element i of a half sits in lane i % 8 of the slot's group, bit
+            // i / 8 of that lane's mask; a 64-bit output word gathers one byte
+            // of each of the 8 lanes and transposes the 8 x 8 bits.
+            constexpr int NH = Sh::ROOT_LEAF ? N : N / 2;
+            const int64_t f = f0 + c.ds;
+            const bool mine = c.lg == 0 && c.ds < nf;
+#pragma unroll
+            for (int h = 0; h < N / NH; h++) {
+                const uint64_t mask = found ? (h == 0 ? r.xlo : r.xhi) : 0ull;
+#pragma unroll
+                for (int w = 0; w < NH / 64; w++) {
+                    uint64_t v = ((mask >> (8 * w)) & 0xFFull) << (8 * c.lg);
+                    v |= xor_lanes<1>(v);
+                    v |= xor_lanes<2>(v);
+                    v |= xor_lanes<4>(v);
+                    v = transpose8x8(v);
+                    if (mine)
+                        *(uint64_t *)(args.out_bits + f * (N / 8) + (h * NH + 64 * w) / 8) = v;
+                }
+            }
+            if (args.out_pm && mine)
+                args.out_pm[f] = pmin;
+            wave_sync();
+            return;
+        }
+    }
     const int invmap = from_lane(r.invmap, (c.ds * L + lstar) * G);
     uint64_t *xb = (uint64_t *)(slice + Pk::O_XB) + c.ds * 2 * G;
     if (c.g == lstar) {
