@@ -30,10 +30,10 @@ namespace rmdec {
 
 constexpr int kWave = 64;
 
-// Words per stored affine map: col[0..11], b at [12] (both times 4: byte
-// offsets of float elements), m at [13].
-constexpr int kMapWords = 16;
-constexpr int kMapB = 12;
+// Words per stored affine map: col[0..9] and b at [10] (both times 4: byte
+// offsets of float elements), the dimension m at [11]; three 16-byte words.
+constexpr int kMapWords = 12;
+constexpr int kMapB = 10;
 
 struct KernelArgs {
     const float *llr;
@@ -322,10 +322,13 @@ struct Shape {
     // byte offsets of the per-wave LDS slice; per-decoder arrays are [D][...]
     static constexpr int O_Y = 0;
     static constexpr int O_MAPS = align16(O_Y + 4 * N);
-    // y at the slice start and the staging area aligned to 4N bytes (slices are
-    // a multiple of 4N) so that byte addresses of map images can be formed by XOR
-    static constexpr int O_STAGE = ((O_MAPS + 4 * kMapWords * MAPS_PER_DEC * D + 4 * N - 1) / (4 * N)) * (4 * N);
+    // y at the slice start and the staging area (permutation nodes below the
+    // root) aligned to 4N bytes (slices are a multiple of 4N) so that byte
+    // addresses of map images can be formed by XOR
     static constexpr int STAGE_BYTES = NPERM >= 2 ? 4 * D * L * N / 2 : 0;
+    static constexpr int O_STAGE = STAGE_BYTES > 0
+                                       ? ((O_MAPS + 4 * kMapWords * MAPS_PER_DEC * D + 4 * N - 1) / (4 * N)) * (4 * N)
+                                       : align16(O_MAPS + 4 * kMapWords * MAPS_PER_DEC * D);
     static constexpr int O_CPM = align16(O_STAGE + STAGE_BYTES); // list merges: metrics
     static constexpr int O_CINF = O_CPM + 4 * D * L * L;          // list merges: payload
     static constexpr int O_CAUX = O_CINF + 4 * D * L * L;         // list merges: payload 2

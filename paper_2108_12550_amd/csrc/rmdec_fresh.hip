@@ -121,14 +121,13 @@ __device__ __forceinline__ void store_map(const CMap &a, int md, uint32_t *out)
     uint4 *o = (uint4 *)out;
     o[0] = make_uint4(a.col[0] << 2, a.col[1] << 2, a.col[2] << 2, a.col[3] << 2);
     o[1] = make_uint4(a.col[4] << 2, a.col[5] << 2, a.col[6] << 2, a.col[7] << 2);
-    o[2] = make_uint4(a.col[8] << 2, a.col[9] << 2, 0u, 0u);
-    o[3] = make_uint4(a.b << 2, (uint32_t)md, 0u, 0u);
+    o[2] = make_uint4(a.col[8] << 2, a.col[9] << 2, a.b << 2, (uint32_t)md);
 }
 
 __device__ __forceinline__ void load_map(const uint32_t *in, CMap &a)
 {
     const uint4 *s = (const uint4 *)in;
-    const uint4 w0 = s[0], w1 = s[1], w2 = s[2], w3 = s[3];
+    const uint4 w0 = s[0], w1 = s[1], w2 = s[2];
     a.col[0] = w0.x >> 2;
     a.col[1] = w0.y >> 2;
     a.col[2] = w0.z >> 2;
@@ -139,7 +138,7 @@ __device__ __forceinline__ void load_map(const uint32_t *in, CMap &a)
     a.col[7] = w1.w >> 2;
     a.col[8] = w2.x >> 2;
     a.col[9] = w2.y >> 2;
-    a.b = w3.x >> 2;
+    a.b = w2.z >> 2;
 }
 
 // (p o q)(i) = A_p (A_q i + b_q) + b_p

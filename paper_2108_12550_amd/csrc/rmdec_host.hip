@@ -226,7 +226,7 @@ void store_table(const std::vector<uint32_t> &q, int m, uint32_t *out)
     for (int k = 0; k < m; k++)
         out[k] = (q[1u << k] ^ q[0]) << 2;
     out[kMapB] = q[0] << 2;
-    out[13] = (uint32_t)m;
+    out[kMapB + 1] = (uint32_t)m;
 }
 
 std::vector<uint32_t> table_of(const Affine &a)
