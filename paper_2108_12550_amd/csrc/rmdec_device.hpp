@@ -329,10 +329,7 @@ struct Shape {
     static constexpr int O_STAGE = STAGE_BYTES > 0
                                        ? ((O_MAPS + 4 * kMapWords * MAPS_PER_DEC * D + 4 * N - 1) / (4 * N)) * (4 * N)
                                        : align16(O_MAPS + 4 * kMapWords * MAPS_PER_DEC * D);
-    static constexpr int O_CPM = align16(O_STAGE + STAGE_BYTES); // list merges: metrics
-    static constexpr int O_CINF = O_CPM + 4 * D * L * L;          // list merges: payload
-    static constexpr int O_CAUX = O_CINF + 4 * D * L * L;         // list merges: payload 2
-    static constexpr int O_SLOT = O_CAUX + 4 * D * L * L;         // survivors
+    static constexpr int O_SLOT = align16(O_STAGE + STAGE_BYTES); // survivors of a map selection
     static constexpr int O_SPCA = O_SLOT + 4 * D * L;             // SPC: |alpha| at o_t [D*L][TAU+1]
     static constexpr int O_SPCI = O_SPCA + 4 * D * L * (TAU + 1); // SPC: o_t [D*L][TAU+1]
     static constexpr int O_SPCP = O_SPCI + 4 * D * L * (TAU + 1); // SPC: parity | hd(o_0) << 1
@@ -361,10 +358,6 @@ struct Ctx {
     __device__ uint32_t *maps_all() const { return (uint32_t *)(base + S::O_MAPS); }
     __device__ uint32_t *maps() const { return maps_all() + moff; }
     __device__ float *stage() const { return (float *)(base + S::O_STAGE); }
-    __device__ float *cpm_all() const { return (float *)(base + S::O_CPM); }
-    __device__ float *cpm() const { return cpm_all() + ds * L * L; }
-    __device__ uint32_t *cinf() const { return (uint32_t *)(base + S::O_CINF) + ds * L * L; }
-    __device__ uint32_t *caux() const { return (uint32_t *)(base + S::O_CAUX) + ds * L * L; }
     __device__ int *slot_all() const { return (int *)(base + S::O_SLOT); }
     __device__ int *slot() const { return slot_all() + ds * L; }
     __device__ float *spca() const { return (float *)(base + S::O_SPCA) + ds * L * (S::TAU + 1); }
@@ -464,6 +457,27 @@ __device__ __forceinline__ double bitonic_sort(double key, int k)
         return key;
     else
         return bitonic_sort_step<NB, G, 1, 0>(key, k);
+}
+
+// Bitonic sort, ascending, of 2^NB keys held one per lane in consecutive
+// lanes: key k in lane base + k (base a multiple of 16, so every partner
+// k ^ ST, ST <= 8, is a DPP move within a row; lanes past the keys sort
+// copies that nobody reads).
+template <int NB, int SZ, int ST>
+__device__ __forceinline__ double bitonic_rows_step(double key, int k)
+{
+    const double o = xor64<ST>(key);
+    const bool asc = SZ == (1 << NB) || (k & SZ) == 0;
+    const bool lower = (k & ST) == 0;
+    // keys are distinct: keep this lane's key if it is on the side the lane wants
+    const bool keep = (key < o) == (lower == asc);
+    const double r = keep ? key : o;
+    if constexpr (ST > 1)
+        return bitonic_rows_step<NB, SZ, ST / 2>(r, k);
+    else if constexpr (SZ < (1 << NB))
+        return bitonic_rows_step<NB, SZ * 2, SZ>(r, k);
+    else
+        return r;
 }
 
 // Byte addresses of elements p(i), i = lg + G j (j < RR), of a vector at
@@ -950,14 +964,35 @@ __device__ __forceinline__ NodeRes<(1 << S), kWave / (L * D)> spcl(const Ctx<M, 
         const float at = spca[src * TS + t];
         const float as0 = spca[src * TS];
         const float fpm = (cur + at) + (p ? -as0 : as0);
-        const int e = 2 * g + (lg & 1);
-        const uint32_t st = (lg & 1) ? ((flips | (1u << t)) << 8) | ((uint32_t)src << 1) | (p ^ 1u)
-                                     : (flips << 8) | ((uint32_t)src << 1) | p;
-        double key = __longlong_as_double(
-            (long long)(((uint64_t)__float_as_uint((lg & 1) ? fpm : cur) << 32) | ((uint32_t)e << 24) | st));
-        key = bitonic_sort<ilog2(2 * L), G>(key, e);
-        // this group's path takes rank g
-        const uint64_t sk = (uint64_t)__double_as_longlong(from_lane(key, c.lead_of(g >> 1) + (g & 1)));
+        uint64_t sk;
+        if constexpr (L >= 8) {
+            static_assert((L * G) % 16 == 0, "the decoder's lanes start at a multiple of 16");
+            // 2L >= 16 candidates: candidate e in lane base + e of the
+            // decoder's lanes, where every exchange of the sort is a DPP move
+            // (in the path groups' own lanes, the strides 4 and 8 of the
+            // candidate index would be lane distances 16 and 32)
+            const int kc = c.lane - c.lead_of(0);
+            const int e = kc & (2 * L - 1);
+            const int from = c.lead_of(e >> 1);
+            const uint32_t stw = (flips << 8) | ((uint32_t)src << 1) | p;
+            const float mc = from_lane(cur, from), mf = from_lane(fpm, from);
+            const uint32_t sc = from_lane(stw, from);
+            const uint32_t st = (e & 1) ? sc ^ ((1u << (t + 8)) | 1u) : sc;
+            double key = __longlong_as_double(
+                (long long)(((uint64_t)__float_as_uint((e & 1) ? mf : mc) << 32) | ((uint32_t)e << 24) | st));
+            key = bitonic_rows_step<ilog2(2 * L), 2, 1>(key, kc);
+            // this group's path takes rank g
+            sk = (uint64_t)__double_as_longlong(from_lane(key, c.lead_of(0) + g));
+        } else {
+            const int e = 2 * g + (lg & 1);
+            const uint32_t st = (lg & 1) ? ((flips | (1u << t)) << 8) | ((uint32_t)src << 1) | (p ^ 1u)
+                                         : (flips << 8) | ((uint32_t)src << 1) | p;
+            double key = __longlong_as_double(
+                (long long)(((uint64_t)__float_as_uint((lg & 1) ? fpm : cur) << 32) | ((uint32_t)e << 24) | st));
+            key = bitonic_sort<ilog2(2 * L), G>(key, e);
+            // this group's path takes rank g
+            sk = (uint64_t)__double_as_longlong(from_lane(key, c.lead_of(g >> 1) + (g & 1)));
+        }
         cur = __uint_as_float((uint32_t)(sk >> 32));
         p = (uint32_t)sk & 1u;
         src = (int)(((uint32_t)sk >> 1) & 0x7Fu);

@@ -56,7 +56,7 @@ constexpr int decoders_per_wave(int M, int L)
 }
 constexpr int waves_per_eu(int M, int R, int L)
 {
-    return M >= 10 && L >= 8 ? 2 : (M == 9 && R == 2 && L == 4) ? 4 : 3;
+    return M >= 10 && L >= 8 ? 2 : ((M == 9 && R == 2 && L == 4) || (M == 8 && R == 3 && L == 8)) ? 4 : 3;
 }
 
 template <int M, int R, int L, int D = decoders_per_wave(M, L), int WPE = waves_per_eu(M, R, L)>
