@@ -163,11 +163,16 @@ const char *rm_last_error(void);
 /*
  * Fused mixed-code launch: frames of several codes (decoders created above)
  * decoded by ONE persistent kernel launch.  The host cuts every segment into
- * runs of `tile_frames` frames and interleaves the runs of all segments
- * round-robin into one work queue (equal segment sizes give a 1:1:...:1
- * interleave); the persistent grid drains the queue.  Per frame the result
- * is exactly that of rm_decode_batch with the segment's decoder (Alg. 5 over
- * Alg. 2-4 and the SPC rules).
+ * runs of `tile_frames` frames and queues the segments' runs in descending
+ * order of the work of one of their frames (P decoders of L paths over
+ * N log2 N), so that the most expensive entries are taken first; the last
+ * frames of the last (cheapest) segment, up to twice the persistent grid's
+ * wavefronts and as far as max_tiles leaves room, get one entry each, so
+ * that the waves run out of work together.  A launch needs
+ * sum_i ceil(n_frames_i / tile_frames_i) <= max_tiles entries.  The
+ * persistent grid drains the queue.  Per frame the result is exactly that
+ * of rm_decode_batch with the segment's decoder (Alg. 5 over Alg. 2-4 and
+ * the SPC rules).
  */
 typedef struct rm_mixed rm_mixed;
 

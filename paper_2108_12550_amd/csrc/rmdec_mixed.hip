@@ -107,31 +107,100 @@ void drop_graph(rm_mixed *mx)
     free_queue(mx->gq);
 }
 
-// Runs of the segments of one launch: segment i is cut into runs[i] runs of
-// tf[i] frames (the last may be shorter); the runs of all segments are
-// interleaved round-robin, run q of every segment that has one, in segment
-// order, before run q + 1 of any.
-struct Runs {
-    int64_t runs[kMaxSegments];
-    int64_t n_frames[kMaxSegments];
-    uint32_t tf[kMaxSegments];
+// Queue of one launch.  The segments are taken in descending order of the
+// work of one of their frames (P decoders of L paths over N log N), so that
+// the most expensive entries are claimed first and the cheapest last
+// (longest processing time first); each is cut into runs of its tile_frames
+// frames, except that the last `tail` frames of the last segment in that
+// order get one entry each, so the waves run out of work within about one
+// of its frames of each other.  Segments without frames come first and add
+// no entries.  Entry k of the queue is a function of k (tile_at), which the
+// host and the no-alloc path's fill kernel both evaluate.
+struct QueuePlan {
     int n_segs;
-    int64_t total, longest;
+    int order[kMaxSegments];          // segment at queue position j
+    int64_t n_frames[kMaxSegments];   // by segment index
+    uint32_t tf[kMaxSegments];        // by segment index
+    int64_t split;                    // frames of the last position cut into runs; the rest one per entry
+    int64_t start[kMaxSegments + 1];  // first entry of position j; start[n_segs] = entries in all
 };
 
-// Validate the segments and fill the per-segment kernel arguments and runs.
-int check_segments(const rm_segment *segs, int n_segs, MixedArgs &a, Runs &ru)
+__host__ __device__ inline Tile tile_at(const QueuePlan &p, int64_t k)
+{
+    int j = 0;
+    while (j + 1 < p.n_segs && k >= p.start[j + 1])
+        j++;
+    const int i = p.order[j];
+    const int64_t tf = p.tf[i];
+    const int64_t lim = j == p.n_segs - 1 ? p.split : p.n_frames[i];
+    const int64_t runs = (lim + tf - 1) / tf;
+    const int64_t r = k - p.start[j];
+    if (r < runs) {
+        const int64_t first = r * tf;
+        return Tile{(uint32_t)i, (uint32_t)first, (uint32_t)(lim - first < tf ? lim - first : tf), 0u};
+    }
+    return Tile{(uint32_t)i, (uint32_t)(lim + (r - runs)), 1u, 0u};
+}
+
+// Segment order and entry counts, for a persistent grid of `waves` waves and
+// a queue of `cap` entries: the single-frame tail is at most 2 * waves frames
+// and only as long as the queue has room for (none if even the plain runs
+// exceed cap, which the callers then reject).
+void plan_queue(QueuePlan &p, const MixedArgs &a, int64_t waves, int64_t cap)
+{
+    double cost[kMaxSegments];
+    for (int i = 0; i < p.n_segs; i++) {
+        const int m = kFused[a.code[i]][0];
+        cost[i] = p.n_frames[i] > 0 ? (double)a.seg[i].P * kFused[a.code[i]][2] * (double)(1 << m) * m : -1.0;
+        p.order[i] = i;
+    }
+    for (int i = 1; i < p.n_segs; i++) // stable insertion sort, empty segments first, then most expensive first
+        for (int j = i; j > 0; j--) {
+            const int x = p.order[j], y = p.order[j - 1];
+            const bool before = cost[x] < 0.0 ? cost[y] >= 0.0 : (cost[y] >= 0.0 && cost[x] > cost[y]);
+            if (!before)
+                break;
+            p.order[j] = y;
+            p.order[j - 1] = x;
+        }
+    const int last = p.order[p.n_segs - 1];
+    const int64_t n = p.n_frames[last], tf = p.tf[last];
+    int64_t others = 0;
+    for (int j = 0; j + 1 < p.n_segs; j++)
+        others += (p.n_frames[p.order[j]] + p.tf[p.order[j]] - 1) / p.tf[p.order[j]];
+    // entries with the last t frames one per entry: non-decreasing in t
+    auto entries = [&](int64_t t) { return others + (n - t + tf - 1) / tf + t; };
+    int64_t lo = 0, hi = 2 * waves < n ? 2 * waves : n;
+    if (entries(0) > cap)
+        hi = 0;
+    while (lo < hi) { // largest t <= hi with entries(t) <= cap
+        const int64_t mid = (lo + hi + 1) / 2;
+        if (entries(mid) <= cap)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    p.split = n - lo;
+    p.start[0] = 0;
+    for (int j = 0; j < p.n_segs; j++) {
+        const int i = p.order[j];
+        const int64_t lim = j == p.n_segs - 1 ? p.split : p.n_frames[i];
+        p.start[j + 1] = p.start[j] + (lim + p.tf[i] - 1) / p.tf[i] + (p.n_frames[i] - lim);
+    }
+}
+
+// Validate the segments and fill the per-segment kernel arguments and the
+// plan's frame counts and run lengths.
+int check_segments(const rm_segment *segs, int n_segs, MixedArgs &a, QueuePlan &p)
 {
     if (!segs)
         return fail(RM_E_INVAL, "null argument");
     if (n_segs < 1 || n_segs > RM_MIXED_MAX_SEGMENTS)
         return fail(RM_E_INVAL, "n_segs must be in [1, RM_MIXED_MAX_SEGMENTS]");
     memset(&a, 0, sizeof a);
-    memset(&ru, 0, sizeof ru);
-    ru.n_segs = n_segs;
-    int64_t *runs = ru.runs;
-    uint32_t *tf = ru.tf;
-    int64_t total = 0, longest = 0;
+    memset(&p, 0, sizeof p);
+    p.n_segs = n_segs;
+    uint32_t *tf = p.tf;
     for (int i = 0; i < n_segs; i++) {
         const rm_segment &g = segs[i];
         if (!g.dec)
@@ -161,38 +230,8 @@ int check_segments(const rm_segment *segs, int n_segs, MixedArgs &a, Runs &ru)
         }
         a.seg[i] = batch_args(g.dec, g.llr, g.n_frames, g.out_bits, g.out_metric);
         a.code[i] = slot;
-        ru.n_frames[i] = g.n_frames;
-        runs[i] = (g.n_frames + tf[i] - 1) / tf[i];
-        total += runs[i];
-        longest = runs[i] > longest ? runs[i] : longest;
+        p.n_frames[i] = g.n_frames;
     }
-    ru.total = total;
-    ru.longest = longest;
-    return RM_OK;
-}
-
-// Validate, fill the kernel arguments and build the queue entries on the host.
-int prepare(rm_mixed *mx, const rm_segment *segs, int n_segs, MixedArgs &a, std::vector<Tile> &tiles)
-{
-    if (!mx)
-        return fail(RM_E_INVAL, "null launcher");
-    Runs ru;
-    int rc = check_segments(segs, n_segs, a, ru);
-    if (rc != RM_OK)
-        return rc;
-    if (ru.total > mx->q.cap)
-        return fail(RM_E_INVAL, "more queue entries than the launcher was created for");
-    tiles.clear();
-    tiles.reserve((size_t)ru.total);
-    for (int64_t q = 0; q < ru.longest; q++)
-        for (int i = 0; i < n_segs; i++)
-            if (q < ru.runs[i]) {
-                const int64_t first = q * ru.tf[i];
-                const int64_t cnt = ru.n_frames[i] - first < ru.tf[i] ? ru.n_frames[i] - first : ru.tf[i];
-                tiles.push_back(Tile{(uint32_t)i, (uint32_t)first, (uint32_t)cnt, 0u});
-            }
-    a.n_tiles = (uint32_t)tiles.size();
-    a.waves = mx->waves ? mx->waves : 2;
     return RM_OK;
 }
 
@@ -212,6 +251,27 @@ int occupancy_blocks(int device, int waves)
 int grid_blocks(rm_mixed *mx, int waves)
 {
     return mx->blocks ? mx->blocks : occupancy_blocks(mx->device, waves);
+}
+
+// Validate, fill the kernel arguments and build the queue entries on the host.
+int prepare(rm_mixed *mx, const rm_segment *segs, int n_segs, MixedArgs &a, std::vector<Tile> &tiles)
+{
+    if (!mx)
+        return fail(RM_E_INVAL, "null launcher");
+    QueuePlan p;
+    int rc = check_segments(segs, n_segs, a, p);
+    if (rc != RM_OK)
+        return rc;
+    a.waves = mx->waves ? mx->waves : 2;
+    plan_queue(p, a, (int64_t)grid_blocks(mx, a.waves) * a.waves, mx->q.cap);
+    const int64_t total = p.start[n_segs];
+    if (total > mx->q.cap)
+        return fail(RM_E_INVAL, "more queue entries than the launcher was created for");
+    tiles.resize((size_t)total);
+    for (int64_t k = 0; k < total; k++)
+        tiles[(size_t)k] = tile_at(p, k);
+    a.n_tiles = (uint32_t)total;
+    return RM_OK;
 }
 
 // Queue the head reset and the persistent kernel on the launcher's stream.
@@ -500,33 +560,15 @@ constexpr int kHeadWords = 64; // the head counter, alone in the first 256 bytes
 // [head, pad .. ][Tile x kStaticTiles]: 256 B + 8 MiB on every device the library runs on
 __device__ __align__(256) uint32_t scratch[kHeadWords + kStaticTiles * (sizeof(Tile) / 4)];
 
-struct StaticFill {
-    int64_t runs[kMaxSegments];
-    int64_t n_frames[kMaxSegments];
-    uint32_t tf[kMaxSegments];
-    int n_segs;
-    int64_t longest;
-};
-
-// Writes the queue of check_segments' round-robin interleave (thread q: run q
-// of every segment that has one, at the entry after all runs of rounds < q)
-// and clears the head, so the fill and the decode can sit in a captured graph.
-__global__ void rm_fill_static_queue(StaticFill f, Tile *tiles, uint32_t *head)
+// Writes the queue entries of the plan (thread k: entry k) and clears the
+// head, so the fill and the decode can sit in a captured graph.
+__global__ void rm_fill_static_queue(QueuePlan p, Tile *tiles, uint32_t *head)
 {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q == 0)
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k == 0)
         *head = 0u;
-    if (q >= f.longest)
-        return;
-    int64_t k = 0;
-    for (int i = 0; i < f.n_segs; i++)
-        k += q < f.runs[i] ? q : f.runs[i];
-    for (int i = 0; i < f.n_segs; i++)
-        if (q < f.runs[i]) {
-            const int64_t first = q * f.tf[i];
-            const int64_t left = f.n_frames[i] - first;
-            tiles[k++] = Tile{(uint32_t)i, (uint32_t)first, (uint32_t)(left < f.tf[i] ? left : f.tf[i]), 0u};
-        }
+    if (k < p.start[p.n_segs])
+        tiles[k] = tile_at(p, k);
 }
 
 // Device address of `scratch` on each device, looked up once per device with
@@ -565,14 +607,10 @@ extern "C" int rm_mixed_decode_static(const rm_segment *segs, int n_segs, int wa
     if ((size_t)waves * kFusedBytes > 65536)
         return fail(RM_E_UNSUPPORTED, "LDS slices do not fit the requested waves per block");
     MixedArgs a;
-    Runs ru;
-    int rc = check_segments(segs, n_segs, a, ru);
+    QueuePlan p;
+    int rc = check_segments(segs, n_segs, a, p);
     if (rc != RM_OK)
         return rc;
-    if (ru.total > kStaticTiles)
-        return fail(RM_E_INVAL, "more queue entries than RM_MIXED_STATIC_MAX_TILES (use larger tile_frames)");
-    if (ru.total == 0)
-        return RM_OK;
     int device = 0;
     hipError_t e = hipGetDevice(&device);
     if (e != hipSuccess)
@@ -582,25 +620,21 @@ extern "C" int rm_mixed_decode_static(const rm_segment *segs, int n_segs, int wa
     rc = static_scratch(device, waves, &base, &blocks);
     if (rc != RM_OK)
         return rc;
-    StaticFill f;
-    memset(&f, 0, sizeof f);
-    for (int i = 0; i < n_segs; i++) {
-        f.runs[i] = ru.runs[i];
-        f.n_frames[i] = ru.n_frames[i];
-        f.tf[i] = ru.tf[i];
-    }
-    f.n_segs = n_segs;
-    f.longest = ru.longest;
+    plan_queue(p, a, (int64_t)blocks * waves, kStaticTiles);
+    const int64_t total = p.start[n_segs];
+    if (total > kStaticTiles)
+        return fail(RM_E_INVAL, "more queue entries than RM_MIXED_STATIC_MAX_TILES (use larger tile_frames)");
+    if (total == 0)
+        return RM_OK;
     Tile *tiles = (Tile *)(base + kHeadWords);
     const hipStream_t s = (hipStream_t)hip_stream;
-    hipLaunchKernelGGL(rm_fill_static_queue, dim3((unsigned)((ru.longest + 255) / 256)), dim3(256), 0, s, f, tiles,
-                       base);
+    hipLaunchKernelGGL(rm_fill_static_queue, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, p, tiles, base);
     e = hipGetLastError();
     if (e != hipSuccess)
         return fail(RM_E_HIP, std::string("queue fill: ") + hipGetErrorString(e));
     a.tiles = tiles;
     a.head = base;
-    a.n_tiles = (uint32_t)ru.total;
+    a.n_tiles = (uint32_t)total;
     a.waves = waves;
     e = launch_fused(a, blocks, s);
     if (e != hipSuccess)
