@@ -320,21 +320,22 @@ struct Shape {
     static constexpr int MAPS_PER_DEC = 2 * L + 4 * L * NPERM;
 
     // byte offsets of the per-wave LDS slice; per-decoder arrays are [D][...]
-    static constexpr int O_Y = 0;
-    static constexpr int O_MAPS = align16(O_Y + 4 * N);
     // y at the slice start and the staging area (permutation nodes below the
-    // root) aligned to 4N bytes (slices are a multiple of 4N) so that byte
-    // addresses of map images can be formed by XOR
+    // root) right after it, both aligned to 4N bytes (slices are a multiple
+    // of 4N) so that byte addresses of map images can be formed by XOR; the
+    // decoders' maps last, so that a frame-packed slice that needs only the
+    // first decoder's copy can end there
+    static constexpr int O_Y = 0;
     static constexpr int STAGE_BYTES = NPERM >= 2 ? 4 * D * L * N / 2 : 0;
-    static constexpr int O_STAGE = STAGE_BYTES > 0
-                                       ? ((O_MAPS + 4 * kMapWords * MAPS_PER_DEC * D + 4 * N - 1) / (4 * N)) * (4 * N)
-                                       : align16(O_MAPS + 4 * kMapWords * MAPS_PER_DEC * D);
+    static constexpr int O_STAGE = O_Y + 4 * N;
     static constexpr int O_SLOT = align16(O_STAGE + STAGE_BYTES); // survivors of a map selection
     static constexpr int O_SPCA = O_SLOT + 4 * D * L;             // SPC: |alpha| at o_t [D*L][TAU+1]
     static constexpr int O_SPCI = O_SPCA + 4 * D * L * (TAU + 1); // SPC: o_t [D*L][TAU+1]
     static constexpr int O_SPCP = O_SPCI + 4 * D * L * (TAU + 1); // SPC: parity | hd(o_0) << 1
     static constexpr int O_XBEST = align16(O_SPCP + 4 * D * L);   // winner's codeword masks, 2G words
-    static constexpr int BYTES = ((O_XBEST + 16 * G + 4 * N - 1) / (4 * N)) * (4 * N);
+    static constexpr int O_MAPS = align16(O_XBEST + 16 * G);      // [D][MAPS_PER_DEC][kMapWords]
+    static constexpr int MAP_BYTES = 4 * kMapWords * MAPS_PER_DEC; // one decoder's maps
+    static constexpr int BYTES = ((O_MAPS + MAP_BYTES * D + 4 * N - 1) / (4 * N)) * (4 * N);
 };
 
 // Per-wave context.  Lane = (decoder ds, path g, lane-in-group lg); the
@@ -1493,10 +1494,35 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
 template <int M, int R, int L, int D>
 struct Packed {
     using S = Shape<M, R, L, D>;
-    static constexpr int O_YX = S::BYTES;                  // y of slots 1 .. D-1, 4N bytes each
-    static constexpr int O_XB = O_YX + 4 * S::N * (D - 1); // [D][2G] winner masks
-    static constexpr int BYTES = ((O_XB + 16 * S::G * D + 4 * S::N - 1) / (4 * S::N)) * (4 * S::N);
-    __host__ __device__ static constexpr uint32_t yoff(uint32_t ds) { return ds == 0 ? 0u : O_YX + 4u * S::N * (ds - 1); }
+    static constexpr int N = S::N;
+    static_assert(D > 1, "frame packing needs several decoder slots per wave");
+    // After the standard slice's y, staging, small arrays and the maps of
+    // one decoder (SHARED: every frame uses the same tables) or of all D
+    // slots: the y of slots 1 .. D-1, 4N bytes each.  The D winners' masks
+    // ([D][2G] words, written once the decoding has stopped reading y)
+    // overlay those copies of y where they fit.
+    static constexpr int yx(bool shared)
+    {
+        return ((S::O_MAPS + S::MAP_BYTES * (shared ? 1 : D) + 4 * N - 1) / (4 * N)) * (4 * N);
+    }
+    static constexpr int XB_BYTES = 16 * S::G * D;
+    static constexpr int xb(bool shared)
+    {
+        return XB_BYTES <= 4 * N * (D - 1) ? yx(shared) : yx(shared) + 4 * N * (D - 1);
+    }
+    static constexpr int bytes(bool shared)
+    {
+        return ((xb(shared) + XB_BYTES > yx(shared) + 4 * N * (D - 1) ? xb(shared) + XB_BYTES
+                                                                       : yx(shared) + 4 * N * (D - 1)) +
+                4 * N - 1) /
+               (4 * N) * (4 * N);
+    }
+    static constexpr int BYTES = bytes(false);        // maps per slot (fresh tables per frame)
+    static constexpr int BYTES_SHARED = bytes(true);  // one copy of the maps
+    __host__ __device__ static constexpr uint32_t yoff(uint32_t ds, bool shared)
+    {
+        return ds == 0 ? 0u : (uint32_t)yx(shared) + 4u * N * (ds - 1);
+    }
 };
 
 // 8 x 8 bit transpose: bit 8b + l of the result is bit 8l + b of x
@@ -1520,6 +1546,7 @@ __device__ __forceinline__ void decode_packed(const KernelArgs &args, int64_t f0
     constexpr int G = Sh::G;
     const int64_t left = args.n_frames - f0;
     const int nf = left < D ? (int)left : D;
+    const bool shared = args.frame_stride == 0;
     wave_sync();
     // each slot's frame (16-byte moves; slots past the last frame repeat
     // frame f0 and their results are not written)
@@ -1531,12 +1558,12 @@ __device__ __forceinline__ void decode_packed(const KernelArgs &args, int64_t f0
             const int t = q / QF;
             const int64_t f = f0 + (t < nf ? t : 0);
             const uint4 v = ((const uint4 *)(args.llr + f * N))[q % QF];
-            *(uint4 *)(slice + Sh::O_Y + Pk::yoff((uint32_t)t) + 16 * (q % QF)) = v;
+            *(uint4 *)(slice + Sh::O_Y + Pk::yoff((uint32_t)t, shared) + 16 * (q % QF)) = v;
         }
     }
     // the decoder's maps: one copy shared by all slots when every frame
     // uses the same tables, else each slot's frame's own
-    const int nmap = args.frame_stride == 0 ? 1 : D;
+    const int nmap = shared ? 1 : D;
     for (int t = 0; t < nmap; t++) {
         const uint4 *mg = (const uint4 *)(args.maps + (f0 + (t < nf ? t : 0)) * args.frame_stride);
         uint4 *ml = (uint4 *)(slice + Sh::O_MAPS) + t * Sh::MAPS_PER_DEC * (kMapWords / 4);
@@ -1547,8 +1574,8 @@ __device__ __forceinline__ void decode_packed(const KernelArgs &args, int64_t f0
     int dlane; // opaque copy of the lane id, as in decode_decoders
     asm volatile("v_mov_b32 %0, %1" : "=v"(dlane) : "v"(lane));
     Ctx<M, R, L, D> c = frame_ctx<M, R, L, D>(args, slice, dlane);
-    c.yoff = Pk::yoff((uint32_t)c.ds);
-    if (args.frame_stride == 0)
+    c.yoff = Pk::yoff((uint32_t)c.ds, shared);
+    if (shared)
         c.moff = 0;
     const RootRes<M, R, L, D> r = decode_root<M, R, L, D>(c);
     // Alg. 5 with one decoder: the first minimum over the list; a frame
@@ -1595,7 +1622,7 @@ __device__ __forceinline__ void decode_packed(const KernelArgs &args, int64_t f0
         }
     }
     const int invmap = from_lane(r.invmap, (c.ds * L + lstar) * G);
-    uint64_t *xb = (uint64_t *)(slice + Pk::O_XB) + c.ds * 2 * G;
+    uint64_t *xb = (uint64_t *)(slice + Pk::xb(shared)) + c.ds * 2 * G;
     if (c.g == lstar) {
         xb[c.lg] = found ? r.xlo : 0ull;
         xb[G + c.lg] = found ? r.xhi : 0ull;
@@ -1608,8 +1635,8 @@ __device__ __forceinline__ void decode_packed(const KernelArgs &args, int64_t f0
         // the winner's inverse map, from the slot's copy in LDS (a frame
         // without a finite metric has all-zero masks, which every map keeps all-zero)
         const uint32_t *mi = (const uint32_t *)(slice + Sh::O_MAPS) +
-                             (args.frame_stride == 0 ? 0 : t * Sh::MAPS_PER_DEC * kMapWords) + bm * kMapWords;
-        emit_masks<M, R, L, D>(mi, best, (const uint64_t *)(slice + Pk::O_XB) + t * 2 * G,
+                             (shared ? 0 : t * Sh::MAPS_PER_DEC * kMapWords) + bm * kMapWords;
+        emit_masks<M, R, L, D>(mi, best, (const uint64_t *)(slice + Pk::xb(shared)) + t * 2 * G,
                                args.out_bits + f * (N / 8), args.out_pm ? args.out_pm + f : nullptr, lane);
     }
     wave_sync();
@@ -1622,10 +1649,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
     const int wave = (int)(threadIdx.x / kWave);
     const int64_t groups = (args.n_frames + D - 1) / D;
     const int64_t stride = (int64_t)gridDim.x * args.waves;
+    const int sbytes = args.frame_stride == 0 ? Pk::BYTES_SHARED : Pk::BYTES;
     for (int64_t gi = xcd_block(blockIdx.x, gridDim.x) * args.waves + wave; gi < groups; gi += stride) {
         uint32_t tid; // opaque per frame group: see rm_mixed_kernel
         asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"(threadIdx.x));
-        decode_packed<M, R, L, D>(args, gi * D, rm_smem + (tid / kWave) * Pk::BYTES, (int)(tid & (kWave - 1)));
+        decode_packed<M, R, L, D>(args, gi * D, rm_smem + (tid / kWave) * sbytes, (int)(tid & (kWave - 1)));
     }
 }
 

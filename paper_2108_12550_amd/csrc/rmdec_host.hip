@@ -433,7 +433,7 @@ rm_decoder *rm_decoder_create_ex(const rm_config *cfg)
     dec->kern = k;
     // one decoder per frame: D frames per wave where a packed kernel exists
     dec->packed = P == 1 && k->launch_packed != nullptr;
-    dec->slice_bytes = dec->packed ? k->lds_bytes_packed : k->lds_bytes_per_wave;
+    dec->slice_bytes = dec->packed ? (fresh ? k->lds_bytes_packed : k->lds_bytes_packed_shared) : k->lds_bytes_per_wave;
     dec->stream = nullptr;
     dec->table_bytes = host.size() * sizeof(uint32_t);
     dec->fresh_chunk = 0;

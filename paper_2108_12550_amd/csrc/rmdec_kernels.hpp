@@ -20,9 +20,11 @@ struct KernelEntry {
     // the workgroup's LDS bytes; 0 for the one-wave-per-frame kernels
     int block_lds_bytes = 0;
     // frame-packed kernel for P = 1 (D frames per wave, one per decoder
-    // slot) and its LDS bytes per wave; null where D = 1
+    // slot) and its LDS bytes per wave with maps per slot (fresh tables per
+    // frame) and with one shared copy; null where D = 1
     LaunchFn launch_packed = nullptr;
     int lds_bytes_packed = 0;
+    int lds_bytes_packed_shared = 0;
 };
 
 template <int M, int R, int L, int D, int WPE>
@@ -36,7 +38,8 @@ hipError_t launch_decode(const KernelArgs &args, int blocks, hipStream_t stream)
 template <int M, int R, int L, int D, int WPE>
 hipError_t launch_packed(const KernelArgs &args, int blocks, hipStream_t stream)
 {
-    const size_t lds = (size_t)args.waves * Packed<M, R, L, D>::BYTES;
+    using Pk = Packed<M, R, L, D>;
+    const size_t lds = (size_t)args.waves * (args.frame_stride == 0 ? Pk::BYTES_SHARED : Pk::BYTES);
     hipLaunchKernelGGL((rm_decode_packed_kernel<M, R, L, D, WPE>), dim3(blocks), dim3(kWave * args.waves), lds, stream,
                        args);
     return hipGetLastError();
@@ -65,7 +68,7 @@ constexpr KernelEntry entry()
     if constexpr (D > 1)
         return KernelEntry{M, R, L, D, Shape<M, R, L, D>::BYTES, Shape<M, R, L, D>::MAPS_PER_DEC,
                            &launch_decode<M, R, L, D, WPE>, 0, &launch_packed<M, R, L, D, WPE>,
-                           Packed<M, R, L, D>::BYTES};
+                           Packed<M, R, L, D>::BYTES, Packed<M, R, L, D>::BYTES_SHARED};
     else
         return KernelEntry{M, R, L, D, Shape<M, R, L, D>::BYTES, Shape<M, R, L, D>::MAPS_PER_DEC,
                            &launch_decode<M, R, L, D, WPE>};
