@@ -558,6 +558,30 @@ __device__ __forceinline__ void spcl_leaf(const BigCtx<M, L> &c, const float *pm
         const int lane = c.tid;
         int cur = 0;
         for (int t = 1; t <= TAU; t++) {
+            if (t > 1) {
+                // From the second split on, the list is in ascending metric
+                // order.  Once every entry's flip scores strictly above every
+                // entry's keep, this split leaves the list as it is, and so
+                // does every later one (an entry's flip metric cannot
+                // decrease with t while its state is unchanged): stop, with
+                // the state in the copy the code after the rounds reads.
+                float kv = -__builtin_inff(), fv = __builtin_inff();
+                if (lane < L) {
+                    const float *aos = c.a(S) + SP(cur)[lane] * n;
+                    kv = CPM(cur)[lane];
+                    fv = (kv + aos[t]) + (1.0f - 2.0f * (float)CP(cur)[lane]) * aos[0];
+                }
+                if (group_reduce<1, kWave, false>(fv) > group_reduce<1, kWave, true>(kv)) {
+                    if (cur != (TAU & 1) && lane < L) {
+                        SP(cur ^ 1)[lane] = SP(cur)[lane];
+                        CP(cur ^ 1)[lane] = CP(cur)[lane];
+                        CPM(cur ^ 1)[lane] = CPM(cur)[lane];
+                        FL(cur ^ 1)[lane] = FL(cur)[lane];
+                    }
+                    wave_sync();
+                    break;
+                }
+            }
             WaveKeys<NK> key;
             if (NK > kWave && t > 1) {
                 // L = 64: after the first round the list is in metric order,
@@ -614,7 +638,7 @@ __device__ __forceinline__ void spcl_leaf(const BigCtx<M, L> &c, const float *pm
         }
     }
     __syncthreads();
-    constexpr int cur = TAU & 1; // the state after TAU rounds
+    constexpr int cur = TAU & 1; // the state after the rounds
     // codewords: hard decisions with the kept flips, o_0 set by Eq. (6)
     uint32_t *xo = c.xb(S, SIDE);
     for (int q = c.tid; q < L * W; q += kThreads) {

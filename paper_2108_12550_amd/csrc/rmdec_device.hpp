@@ -853,6 +853,20 @@ __device__ __forceinline__ NodeRes<(1 << S), kWave / (L * D)> fhtl(const Ctx<M, 
     return {x, opm, (int)((uint32_t)e / K)};
 }
 
+// maximum (MAX) or minimum of v over the lanes lane ^ w, w a multiple of W
+// below E (W, E powers of two): over the path groups of a decoder for W = G,
+// E = G L
+template <int W, int E, bool MAX>
+__device__ __forceinline__ float group_reduce(float v)
+{
+    if constexpr (W >= E) {
+        return v;
+    } else {
+        const float o = xor_lanes<W>(v);
+        return group_reduce<2 * W, E, MAX>(MAX ? fmaxf(v, o) : fminf(v, o));
+    }
+}
+
 // rank of this lane's value among the n values of its group (smaller first,
 // ties to the lower element index); partner element lg ^ w sits in lane ^ w
 template <int W, int n>
@@ -965,6 +979,19 @@ __device__ __forceinline__ NodeRes<(1 << S), kWave / (L * D)> spcl(const Ctx<M, 
         const float at = spca[src * TS + t];
         const float as0 = spca[src * TS];
         const float fpm = (cur + at) + (p ? -as0 : as0);
+        if (t >= 2) {
+            // From the second split on, the list is in ascending (metric,
+            // position) order.  Once every path's flip scores strictly above
+            // every path's keep, this split leaves the list as it is, and so
+            // does every later one: a path's flip metric cannot decrease with
+            // t while its state is unchanged (|alpha| at o_t is
+            // non-decreasing in t, and rounding is monotone).  The wave stops
+            // when that holds for each of its decoders.
+            const float kmax = group_reduce<G, G * L, true>(cur);
+            const float fmin = group_reduce<G, G * L, false>(fpm);
+            if (__builtin_amdgcn_ballot_w64(!(fmin > kmax)) == 0)
+                break;
+        }
         uint64_t sk;
         if constexpr (L >= 8) {
             static_assert((L * G) % 16 == 0, "the decoder's lanes start at a multiple of 16");
