@@ -96,7 +96,9 @@ rm_decoder *rm_decoder_create_ex(const rm_config *cfg);
  *   out_bits   device, n_frames x N/8 bytes: the decoded codeword x_hat,
  *              bit i of frame f at byte f*N/8 + (i>>3), bit (i&7).
  *   out_metric device, n_frames float32 final path metrics, or NULL.
- * Work is queued on the decoder's stream (rm_decoder_set_stream; default the
+ * llr must be 16-byte aligned, out_bits aligned to min(8, N/8) bytes and
+ * out_metric to 4 (RM_E_INVAL otherwise): the kernels move frames in 16-byte
+ * and codewords in 8-byte words.  Work is queued on the decoder's stream (rm_decoder_set_stream; default the
  * null stream) and the call returns without waiting.  n_frames = 0 is a
  * no-op.  Results depend only on (m, r, P, L, seed, perm_mode, llr), and in
  * RM_PERM_FRESH mode also on each frame's index within the call.
@@ -211,7 +213,8 @@ int rm_mixed_set_grid(rm_mixed *mx, int blocks, int waves_per_block);
  * reuse one device queue, so all calls on one launcher must go to one stream
  * (or be ordered by the caller).  Segments whose code is not compiled into
  * the fused kernel give RM_E_UNSUPPORTED; more entries than max_tiles give
- * RM_E_INVAL; host pointers give RM_E_PTR.  Nothing is queued on error.
+ * RM_E_INVAL, as do arrays aligned below rm_decode_batch's rule; host
+ * pointers give RM_E_PTR.  Nothing is queued on error.
  */
 int rm_mixed_decode(rm_mixed *mx, const rm_segment *segs, int n_segs);
 

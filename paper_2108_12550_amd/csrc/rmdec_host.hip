@@ -39,6 +39,20 @@ int check_device_ptr(const void *p, const char *name)
     return RM_OK;
 }
 
+// Alignment of the caller's arrays: frames are read in 16-byte words and
+// codewords written in 8-byte words (bytes below N = 64).
+int check_alignment(int N, const float *llr, const uint8_t *out_bits, const float *out_metric)
+{
+    const uintptr_t bits_align = N / 8 < 8 ? (uintptr_t)(N / 8) : 8u;
+    if ((uintptr_t)llr % 16 != 0)
+        return fail(RM_E_INVAL, "llr must be 16-byte aligned");
+    if ((uintptr_t)out_bits % bits_align != 0)
+        return fail(RM_E_INVAL, "out_bits must be aligned to min(8, N/8) bytes");
+    if ((uintptr_t)out_metric % 4 != 0)
+        return fail(RM_E_INVAL, "out_metric must be 4-byte aligned");
+    return RM_OK;
+}
+
 KernelArgs batch_args(const rm_decoder *d, const float *llr, int64_t n_frames, uint8_t *out_bits, float *out_metric)
 {
     KernelArgs a;
@@ -392,6 +406,10 @@ rm_decoder *rm_decoder_create_ex(const rm_config *cfg)
     const int fresh = cfg->perm_mode == RM_PERM_FRESH;
     const Draw d = fresh ? Draw{{}, {}, spine_perm_nodes(m, r)} : draw_all(m, r, P, L, cfg->seed, pfht);
     const int mpd = 2 * L + 4 * L * d.nperm;
+    if (mpd > k->maps_per_dec) { // the kernels' LDS holds at most maps_per_dec maps per decoder
+        fail(RM_E_UNSUPPORTED, "more maps per decoder than the kernel holds");
+        return nullptr;
+    }
 
     // Per decoder: [0,L) initial maps, [L,2L) their inverses; for spine node v:
     // [2L+4Lv, 2L+4Lv+2L) candidate maps (at v = 0 composed after the initial
@@ -566,6 +584,8 @@ int rm_decode_batch(rm_decoder *d, const float *llr, int64_t n_frames, uint8_t *
         rc = check_device_ptr(out_bits, "out_bits");
     if (rc == RM_OK && out_metric)
         rc = check_device_ptr(out_metric, "out_metric");
+    if (rc == RM_OK)
+        rc = check_alignment(d->N, llr, out_bits, out_metric);
     if (rc != RM_OK)
         return rc;
     if (d->cfg.perm_mode == RM_PERM_FRESH)

@@ -30,6 +30,7 @@ namespace rmdec {
 extern thread_local std::string g_err;
 int fail(int code, const std::string &msg);
 int check_device_ptr(const void *p, const char *name);
+int check_alignment(int N, const float *llr, const uint8_t *out_bits, const float *out_metric);
 KernelArgs batch_args(const rm_decoder *d, const float *llr, int64_t n_frames, uint8_t *out_bits, float *out_metric);
 // launch the decoder's batched kernel over n_frames frames (args from batch_args)
 hipError_t launch_decoder(const rm_decoder *d, const KernelArgs &a, int64_t n_frames);

@@ -225,6 +225,8 @@ int check_segments(const rm_segment *segs, int n_segs, MixedArgs &a, QueuePlan &
                 rc = check_device_ptr(g.out_bits, "out_bits");
             if (rc == RM_OK && g.out_metric)
                 rc = check_device_ptr(g.out_metric, "out_metric");
+            if (rc == RM_OK)
+                rc = check_alignment(g.dec->N, g.llr, g.out_bits, g.out_metric);
             if (rc != RM_OK)
                 return rc;
         }

@@ -172,6 +172,35 @@ def test_integer_llr_ties(m, r, P, L):
     check(m, r, P, L, PFHT, llr, seed=1)
 
 
+@pytest.mark.parametrize("m,r,P,L", [(8, 3, 4, 8), (9, 2, 6, 4), (7, 2, 4, 8)])
+def test_integer_llr_ties_spc_split_stop(m, r, P, L):
+    """The SPC splits stop once every flip scores above every keep; with
+    LLRs in {-2, ..., 2} flips often tie the largest keep exactly, where
+    stopping a split early would go wrong if the rule were not strict."""
+    rng = np.random.default_rng(700 + m * 10 + L)
+    llr = rng.integers(-2, 3, size=(300, 1 << m)).astype(np.float32)
+    check(m, r, P, L, PFHT, llr, seed=5)
+
+
+def test_misaligned_arrays_rejected():
+    """Frames are read in 16-byte and codewords written in 8-byte words: a
+    misaligned array is refused before anything is queued."""
+    dec = rmd.Decoder(7, 2, 1, 1, seed=0, perm_mode=NONE)
+    # 4 frames of RM(2,7): 512 LLRs in, 64 codeword bytes and 4 metrics out;
+    # every buffer below holds that much past each pointer used
+    buf = torch.zeros(4 * 128 + 4, dtype=torch.float32, device="cuda")
+    bits = torch.zeros(4 * 16 + 8, dtype=torch.uint8, device="cuda")
+    pm = torch.zeros(5, dtype=torch.float32, device="cuda")
+    cases = [(buf[1:].data_ptr(), bits[:64].data_ptr(), pm.data_ptr()),   # llr at 4 bytes
+             (buf[:512].data_ptr(), bits[1:].data_ptr(), pm.data_ptr())]  # out_bits at 1 byte
+    for llr_p, bits_p, pm_p in cases:
+        assert rmd.rm_decode_batch(dec._h, llr_p, 4, bits_p, pm_p) == rmd.RM_E_INVAL
+        assert "aligned" in rmd.rm_last_error()
+    assert rmd.rm_decode_batch(dec._h, buf[4:].data_ptr(), 4, bits[8:].data_ptr(), pm[1:].data_ptr()) == rmd.RM_OK
+    torch.cuda.synchronize()
+    dec.close()
+
+
 def test_all_zero_llr():
     llr = np.zeros((9, 512), np.float32)
     check(9, 2, 4, 4, PFHT, llr, seed=2)
