@@ -68,6 +68,8 @@ def lib():
                                             P(ctypes.c_int), ctypes.c_int]
         L.rmo_splitmix64_next.restype = ctypes.c_uint64
         L.rmo_splitmix64_next.argtypes = [P(ctypes.c_uint64)]
+        L.rmo_lm.restype = ctypes.c_float
+        L.rmo_lm.argtypes = [ctypes.c_int, P(ctypes.c_float), ctypes.c_uint32]
         _lib = L
     return _lib
 
@@ -126,6 +128,15 @@ class OracleDecoder:
                                       _p(md, ctypes.c_int), k)
         assert got == k
         return [(rows[i * 16:i * 16 + md[i]].copy(), int(b[i])) for i in range(k)]
+
+
+def lm(v: np.ndarray, d: int) -> float:
+    """Alg. 2's LM of the pairs {u, u ^ d} of v (2^m float32 LLRs, d != 0),
+    summed in the oracle's order (rmo_lm)."""
+    v = np.ascontiguousarray(v, dtype=np.float32)
+    m = int(v.size).bit_length() - 1
+    assert v.size == 1 << m and 0 < d < v.size
+    return float(lib().rmo_lm(m, _p(v, ctypes.c_float), ctypes.c_uint32(d)))
 
 
 def info_set(m: int, r: int) -> np.ndarray:

@@ -240,6 +240,35 @@ static float tree_sum(const float *v, int n)
     return s;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Alg. 2's reliability of a candidate permutation (LM): the sum of |f| over */
+/* the pairs of positions that the candidate's f step combines, where       */
+/* |f(a, b)| = min(|a|, |b|).  Under an affine map p the pairs              */
+/* {p(i), p(i + n/2)}, i < n/2, are the cosets {u, u ^ d} of               */
+/* d = p(n/2) ^ p(0), so the metric depends on the map through d alone.     */
+/* The paper fixes no order for the sum.  Here the cosets are taken in      */
+/* ascending order of their smaller element u in the array v that holds the */
+/* LLRs (u runs over the positions whose bit msb(d) is 0), and the halving  */
+/* tree sums that list: the order in which a decoder reads the pairs        */
+/* straight from the array, without going through the map.                  */
+/* ------------------------------------------------------------------------ */
+float rmo_lm(int m, const float *v, uint32_t d)
+{
+    const int h = 1 << (m - 1);
+    int k = 0;
+    while ((d >> (k + 1)) != 0)
+        k++;
+    float *fv = malloc((size_t)h * sizeof *fv);
+    for (int i = 0; i < h; i++) {
+        const uint32_t lo = (uint32_t)i & ((1u << k) - 1u);
+        const uint32_t u = (((uint32_t)i >> k) << (k + 1)) | lo; /* i with a 0 put in at bit k */
+        fv[i] = fabsf(f_minsum(v[u], v[u ^ d]));
+    }
+    const float s = tree_sum(fv, h);
+    free(fv);
+    return s;
+}
+
 /* Stable ascending insertion sort of the index array ord[] by key[]. */
 static void stable_sort_asc(int *ord, const float *key, int n)
 {
@@ -745,6 +774,8 @@ typedef struct {
     const amap *cand; /* this decoder's candidate maps: [n_perm_nodes][2L] */
     int is_perm;      /* isPermutation */
     int perm_node;    /* index of the next permutation-domain node */
+    const float *y;   /* the received vector, read by the root's LM */
+    const amap *init; /* the paths' initial maps: path l's root LLRs are y[init_l(i)] */
 } ctx_t;
 
 static float **alloc_fvecs(int L, int n)
@@ -789,20 +820,25 @@ static void node_decode(ctx_t *c, int r, int m, float *const *alpha, const float
 
         if (c->is_perm) {
             /* Permutation domain: 2L candidates, candidate cc permutes the LLRs
-             * of path cc mod L; LM = sum |f(permuted)|; keep the L largest. */
+             * of path cc mod L; LM = sum |f(permuted)| (rmo_lm); keep the L
+             * largest.  At the root path l's LLRs are y read through its
+             * initial map, so the pairs are read from y, through the
+             * candidate's map composed after that initial map. */
             is_per = 1;
             cands = &c->cand[(size_t)c->perm_node * 2 * L];
             c->perm_node++;
             float lm[2 * MAXL];
-            float *t = malloc((size_t)n * sizeof *t);
-            float *fv = malloc((size_t)h * sizeof *fv);
             for (int cc = 0; cc < 2 * L; cc++) {
                 const int src = cc % L;
-                for (int i = 0; i < n; i++)
-                    t[i] = alpha[src][amap_apply(&cands[cc], (uint32_t)i)];
-                for (int i = 0; i < h; i++)
-                    fv[i] = fabsf(f_minsum(t[i], t[i + h]));
-                lm[cc] = tree_sum(fv, h);
+                const amap *pc = &cands[cc];
+                if (m == c->dec->m) {
+                    const amap *pi = &c->init[src];
+                    const uint32_t d = amap_apply(pi, amap_apply(pc, (uint32_t)h)) ^ amap_apply(pi, amap_apply(pc, 0));
+                    lm[cc] = rmo_lm(m, c->y, d);
+                } else {
+                    const uint32_t d = amap_apply(pc, (uint32_t)h) ^ amap_apply(pc, 0);
+                    lm[cc] = rmo_lm(m, alpha[src], d);
+                }
             }
             for (int cc = 0; cc < 2 * L; cc++)
                 sel[cc] = cc;
@@ -816,8 +852,6 @@ static void node_decode(ctx_t *c, int r, int m, float *const *alpha, const float
             }
             wa = pa;
             wpm = ppm;
-            free(t);
-            free(fv);
         }
 
         /* left child RM(r-1, m-1) on f */
@@ -919,7 +953,7 @@ int rmo_decode_frame(const rmo_decoder *d, const float *y, int64_t frame, uint8_
              * through the path splits alone. */
             pm0[l] = (d->mode != RMO_PERM_NONE || l == 0) ? 0.0f : INFINITY;
         }
-        ctx_t c = {d, cand, d->mode != RMO_PERM_NONE, 0};
+        ctx_t c = {d, cand, d->mode != RMO_PERM_NONE, 0, y, init};
         node_decode(&c, d->r, m, a, pm0, x, pmo, anc);
         int ls = 0;
         for (int l = 1; l < L; l++)

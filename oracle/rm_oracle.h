@@ -58,6 +58,8 @@ int rmo_spcl(int s, int L, const float *alpha, const float *pm_in,
              uint8_t *x, float *pm, int *anc);                     /* Eqs. (2)-(6) */
 int rmo_fhtl(int s, int L, const float *alpha, const float *pm_in,
              uint8_t *x, float *pm, int *anc);                     /* Alg. 3 */
+float rmo_lm(int m, const float *v, uint32_t d);                   /* Alg. 2's LM of
+                             the pairs {u, u ^ d} of v (2^m floats), d != 0 */
 int rmo_schedule(int m, int r, int perm_mode, int *out, int cap);  /* (kind,r,m) triples */
 int rmo_perm_count(const rmo_decoder *d);
 int rmo_perm_export(const rmo_decoder *d, uint16_t *rows, uint16_t *b, int *mdim, int cap);

@@ -713,24 +713,26 @@ __device__ __forceinline__ void big_node(const BigCtx<M, L> &c, const float *pm_
     uint8_t *orig = c.orig(VP);
     const float *pmL_in = pm_in;
     if (perm) {
-        // LM of the 2L candidates: sum of |f| over the permuted LLRs of path cc mod L
+        // LM of the 2L candidates: sum of |f| over the pairs that candidate
+        // cc's map combines in path cc mod L's LLRs (y at the root, through
+        // the composed maps).  An affine map's pairs {p(i), p(i + h)} are the
+        // cosets {u, u ^ d} of its column d = p(h) ^ p(0); they are summed in
+        // ascending order of u (i with a 0 put in at bit msb(d)) by the
+        // halving tree over i, whose first level is taken here
         constexpr int GH = G / 2;
         const int cc = c.tid / GH, ct = c.tid % GH, src = cc % L;
-        MapR<S> mp;
-        load_map<S>(c.map(2 * L + 4 * L * VP + cc), mp);
+        const uint32_t d = c.map(2 * L + 4 * L * VP + cc)[S - 1] >> 2;
+        const uint32_t hi = 0u - (1u << (31 - __builtin_clz(d)));
         float *scr = ach + cc * (h / 2);
-        constexpr int NIT = (h / 2 + GH - 1) / GH, LS = ilog2(GH);
-        uint32_t p = apply_map<S>(mp, (uint32_t)ct); // p(i), Gray-code walk
+        constexpr int NIT = (h / 2 + GH - 1) / GH;
 #pragma unroll
         for (int it = 0; it < NIT; it++) {
-            if (it > 0)
-                p ^= mp.col[LS + __builtin_ctz(it)];
-            const int i = ct + GH * (it ^ (it >> 1));
+            const int i = ct + GH * it;
             if (i < h / 2) {
-                const uint32_t ph = p ^ mp.col[S - 1], pq = p ^ mp.col[S - 2]; // p(i + h), p(i + h/2)
-                const float v0 = fabsf(big_fminsum(in_llr<M, L, S>(c, src, p), in_llr<M, L, S>(c, src, ph)));
-                const float v1 = fabsf(
-                    big_fminsum(in_llr<M, L, S>(c, src, pq), in_llr<M, L, S>(c, src, pq ^ mp.col[S - 1])));
+                const uint32_t i0 = (uint32_t)i, i1 = (uint32_t)(i + h / 2);
+                const uint32_t u0 = i0 + (i0 & hi), u1 = i1 + (i1 & hi);
+                const float v0 = fabsf(big_fminsum(in_llr<M, L, S>(c, src, u0), in_llr<M, L, S>(c, src, u0 ^ d)));
+                const float v1 = fabsf(big_fminsum(in_llr<M, L, S>(c, src, u1), in_llr<M, L, S>(c, src, u1 ^ d)));
                 scr[i] = v0 + v1;
             }
         }

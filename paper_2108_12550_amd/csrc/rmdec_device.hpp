@@ -1092,10 +1092,18 @@ __device__ __forceinline__ typename Lay<n, G>::Mask combine(typename Lay<n / 2, 
 
 // ---------------------------------------------------------------------------
 // Permutation-domain selection at a node of size 2^MD (Alg. 2): candidate c
-// reads path c mod L through map c; LM_c = sum_i |f| over the halving tree;
-// the L largest survive (ties to the lower c).  src(path) is the LDS byte
-// address of that path's node LLRs.  Returns the candidate that becomes this
-// group's path.
+// reads path c mod L through map c; LM_c = sum of |f| over the pairs the
+// map's f combines; the L largest survive (ties to the lower c).  src(path)
+// is the LDS byte address of that path's node LLRs (y at the root, whose
+// candidate maps are stored composed with the paths' initial maps).  Returns
+// the candidate that becomes this group's path.
+//
+// An affine map's pairs {p(i), p(i + h)} are the cosets {u, u ^ d} of its
+// column d = p(h) ^ p(0): the LM is summed over those cosets in ascending
+// order of their smaller element u (u = i with a 0 put in at bit msb(d)),
+// by the halving tree over i.  Read that way the pairs need no map: a path
+// group's lanes read consecutive words of the node vector and the same
+// words XOR d, with no bank conflicts among them.
 // ---------------------------------------------------------------------------
 template <int M, int R, int L, int D, int MD, class Src>
 __device__ __forceinline__ int perm_select(const Ctx<M, R, L, D> &c, const uint32_t *cand_maps, Src src)
@@ -1109,10 +1117,17 @@ __device__ __forceinline__ int perm_select(const Ctx<M, R, L, D> &c, const uint3
     float lm[2];
 #pragma unroll
     for (int pass = 0; pass < 2; pass++) {
-        const uint32_t *mp = cand_maps + (c.g + L * pass) * kMapWords;
+        // d as a byte offset; element i = lg + G j of the sum list is u(i),
+        // the positions at and above msb(d) moved up by one: byte address
+        // x + (x & -top) for x = 4i, top = the byte value of msb(d)
+        const uint32_t colh = cand_maps[(c.g + L * pass) * kMapWords + MD - 1];
+        const uint32_t hi = 0u - (1u << (31 - __builtin_clz(colh)));
+        const uint32_t x4 = valid ? 4u * (uint32_t)c.lg : 0u;
+        const uint32_t b = src(c.g) + x4 + (x4 & hi);
         uint32_t pos[RR];
-        map_positions<MD - 1, G, RR>(mp, c.lg, src(c.g), pos);
-        const uint32_t colh = mp[MD - 1];
+#pragma unroll
+        for (int j = 0; j < RR; j++)
+            pos[j] = b + (uint32_t)(4 * G * j) + ((uint32_t)(4 * G * j) & hi);
         float v[RR];
 #pragma unroll
         for (int j = 0; j < RR; j++)

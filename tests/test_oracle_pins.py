@@ -166,6 +166,61 @@ def test_fresh_perms_are_automorphisms(m, r, L):
 
 
 # --------------------------------------------------------------------------
+# Alg. 2's LM of a candidate permutation (rmo_lm)
+# --------------------------------------------------------------------------
+
+def _lm_brute(v, d):
+    """Sum over the cosets {u, u ^ d} of min(|v_u|, |v_(u^d)|), exactly."""
+    return sum(min(abs(float(v[u])), abs(float(v[u ^ d]))) for u in range(v.size) if u < (u ^ d))
+
+
+@pytest.mark.parametrize("m", [1, 3, 6, 9])
+def test_lm_is_the_sum_over_the_pairs_of_the_direction(m):
+    """Integer LLRs keep every partial sum exact: the LM equals the sum of
+    min(|a|, |b|) = |f(a, b)| over the cosets of {0, d}, for every d."""
+    rng = np.random.default_rng(40 + m)
+    v = rng.integers(-16, 17, size=1 << m).astype(np.float32)
+    for d in ([1, (1 << m) - 1] + list(rng.integers(1, 1 << m, size=12))):
+        assert oracle.lm(v, int(d)) == _lm_brute(v, int(d))
+
+
+def test_lm_on_real_llrs_within_rounding():
+    rng = np.random.default_rng(45)
+    v = rng.normal(0.0, 2.0, size=512).astype(np.float32)
+    for d in (1, 7, 256, 300, 511):
+        ref = _lm_brute(v, d)
+        assert abs(oracle.lm(v, d) - ref) <= 1e-5 * ref
+
+
+def test_lm_of_a_map_depends_only_on_its_pair_direction():
+    """The pairs an affine map's f combines, {p(i), p(i + n/2)}, are the
+    cosets of d = p(n/2) ^ p(0): for the decoder's own candidate maps the
+    map-order sum of |f| equals the LM at d (exactly, on integer LLRs)."""
+    rng = np.random.default_rng(46)
+    for rows, b in oracle.OracleDecoder(7, 2, 2, 4, seed=5).perms():
+        md = len(rows)
+        n = 1 << md
+        p = [(sum(((bin(int(rows[j]) & i).count("1") & 1) << j) for j in range(md)) ^ b) for i in range(n)]
+        v = rng.integers(-9, 10, size=n).astype(np.float32)
+        h = n // 2
+        by_map = sum(min(abs(float(v[p[i]])), abs(float(v[p[i + h]]))) for i in range(h))
+        assert oracle.lm(v, p[h] ^ p[0]) == by_map
+
+
+def test_lm_at_the_top_direction_is_the_plain_halving_tree():
+    """For d = n/2 the cosets in ascending order are (i, i + n/2), i < n/2:
+    the LM is the halving tree over |f(v_i, v_(i+n/2))| in index order."""
+    rng = np.random.default_rng(47)
+    v = rng.normal(0.0, 2.0, size=256).astype(np.float32)
+    t = np.minimum(np.abs(v[:128]), np.abs(v[128:])).astype(np.float32)
+    w = 64
+    while w >= 1:
+        t[:w] = t[:w] + t[w:2 * w]
+        w //= 2
+    assert oracle.lm(v, 128) == float(t[0])
+
+
+# --------------------------------------------------------------------------
 # O4: FHT decoding (Alg. 4) against brute force over RM(1,s)
 # --------------------------------------------------------------------------
 
