@@ -80,6 +80,19 @@ def measured_traffic(path=TRAFFIC_FILE, sources=KERNEL_SOURCES):
         return None
 
 
+def copy_calibration(dev, stream):
+    """A plain 1 GiB device copy, for scaling the HBM counters of a profiled
+    run (what FETCH_SIZE and WRITE_SIZE read for known bytes)."""
+    import torch
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    with torch.cuda.stream(stream):
+        dst.copy_(src)
+    stream.synchronize()
+    del src, dst
+    log("copy calibration: 1 GiB read + 1 GiB written")
+
+
 def fer_ci(errors: int, n: int, z: float = 1.96):
     """Frame error rate with its Wilson score interval (95% for z = 1.96)."""
     p = errors / n
@@ -219,13 +232,7 @@ def bench_headline(args):
             for _ in EBN0]
 
     if args.copy_calibration:
-        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        with torch.cuda.stream(stream):
-            dst.copy_(src)
-        stream.synchronize()
-        del src, dst
-        log("copy calibration: 1 GiB read + 1 GiB written")
+        copy_calibration(dev, stream)
 
     def step(i):
         b = i % len(EBN0)
@@ -606,6 +613,8 @@ def bench_c1(args, dev, stream):
     import synth
     m, r = 7, 2
     N = 1 << m
+    if args.copy_calibration:
+        copy_calibration(dev, stream)
     dec = rmd.Decoder(m, r, 1, 1, seed=SEED, perm_mode=rmd.RM_PERM_NONE)
     x, llr = synth.frames(m, r, 10000, 3.0, seed=0)
     bits, _ = dec.decode(torch.from_numpy(llr).to(dev), stream=stream)
