@@ -302,7 +302,7 @@ MIXED_CODES = [(7, 2, 8, 4), (8, 2, 16, 4), (9, 2, 20, 4), (10, 2, 32, 4)]  # (m
 # per-frame algorithmic ops of each code's decoder set (op model of the
 # paper's complexity count: f/g, LM, FHT, selection, SPC, times P)
 MIXED_OPS = {7: 3.58e4, 8: 1.56e5, 9: 4.27e5, 10: 1.49e6}
-MIXED_KERNEL = "rm_mixed_kernel<3, Code<7,2,4,4>, Code<8,2,4,4>, Code<9,2,4,2>, Code<10,2,4,1>>"
+MIXED_KERNEL = "rm_mixed_kernel<4, Code<7,2,4,4>, Code<8,2,4,4>, Code<9,2,4,2>, Code<10,2,4,1>>"
 MIXED_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rm_mixed_c4_traffic.txt")
 MIXED_SOURCES = [os.path.join(ROOT, "paper_2108_12550_amd", "csrc", f)
                  for f in ("rmdec_device.hpp", "rmdec_mixed.hip")]

@@ -51,15 +51,17 @@ hipError_t launch_packed(const KernelArgs &args, int blocks, hipStream_t stream)
 // lanes per path), which keeps a half-length node vector at 32 registers.
 // WPE: wavefronts per SIMD the register allocation must allow (4: at most
 // 128 VGPRs; 3: 168; 2: 256).  These choices keep every kernel free of (or
-// nearly free of) register spills; RM(2,9) at L = 4 holds 123 VGPRs under
-// the cap of four waves per SIMD and spills nothing.
+// nearly free of) register spills; RM(2,9) and RM(2,10) at L = 4 and RM(3,8)
+// at L = 8 fit the cap of four waves per SIMD without spilling.
 constexpr int decoders_per_wave(int M, int L)
 {
     return L >= 8 ? 1 : (M >= 10 ? 4 : (M <= 8 && L == 4) ? 16 : 8) / L;
 }
 constexpr int waves_per_eu(int M, int R, int L)
 {
-    return M >= 10 && L >= 8 ? 2 : ((M == 9 && R == 2 && L == 4) || (M == 8 && R == 3 && L == 8)) ? 4 : 3;
+    return M >= 10 && L >= 8 ? 2
+           : ((M == 9 && R == 2 && L == 4) || (M == 10 && R == 2 && L == 4) || (M == 8 && R == 3 && L == 8)) ? 4
+                                                                                                            : 3;
 }
 
 template <int M, int R, int L, int D = decoders_per_wave(M, L), int WPE = waves_per_eu(M, R, L)>

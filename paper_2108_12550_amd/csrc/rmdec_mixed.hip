@@ -19,9 +19,9 @@ namespace {
 // The codes compiled into the fused kernel: RM(2,7), RM(2,8), RM(2,9) and
 // RM(2,10), list size 4; four decoders per wavefront for RM(2,7) and
 // RM(2,8), two for RM(2,9), one for RM(2,10) (the per-code kernels make the
-// same choices).  Under the cap of 3 waves per SIMD the four bodies
-// together hold 128 VGPRs, so the kernel runs 4 waves per SIMD.
-constexpr int kWPE = 3;
+// same choices).  The four bodies are held to 128 VGPRs, 4 waves per SIMD
+// like the per-code kernels (left to the cap of 3 they take 132 and run 3).
+constexpr int kWPE = 4;
 
 constexpr int kFused[][3] = {{7, 2, 4}, {8, 2, 4}, {9, 2, 4}, {10, 2, 4}};
 constexpr int kNumFused = 4;
