@@ -90,5 +90,9 @@ KernelTable kernels_codes_e();
 KernelTable kernels_codes_f();
 KernelTable kernels_codes_g(); // lists of 16, 32 and 64 paths
 KernelTable kernels_codes_h(); // lists of 64 paths, N = 512
+KernelTable kernels_codes_i(); // the rest of m <= 10, L <= 8, by length
+KernelTable kernels_codes_j();
+KernelTable kernels_codes_k();
+KernelTable kernels_codes_l();
 
 } // namespace rmdec

@@ -105,6 +105,20 @@ def test_leaf_roots(m, r, L):
     check(m, r, 2, L, PFHT, llr, seed=3)
 
 
+# every (m, r, L <= 8) built for the rest of the domain: leaf roots, higher
+# orders, lists of 2 and 8 (the shapes above cover the others)
+DOMAIN_REST = [(m, r, L) for m in range(3, 11) for r in range(1, m) for L in (1, 2, 4, 8)
+               if (m, r, L) not in {(10, 1, 8), (10, 9, 8)}]
+
+
+@pytest.mark.parametrize("m,r,L", DOMAIN_REST)
+def test_whole_domain(m, r, L):
+    """Each built shape against the oracle: 2 decoders, 24 frames at 1.5 dB
+    (with frame errors), permuted mode."""
+    _, llr = synth.frames(m, r, 24, 1.5, seed=900 + 16 * m + r)
+    check(m, r, 2, L, PFHT, llr, seed=L + 3)
+
+
 @pytest.mark.parametrize("m,r", [(9, 3), (9, 4), (8, 4)])
 @pytest.mark.parametrize("L", [1, 2, 4, 8])
 def test_higher_order_codes(m, r, L):
