@@ -28,7 +28,10 @@ namespace rmdec {
 namespace big {
 
 constexpr int kThreads = 512;
-constexpr int kMaxPerm = 3; // permutation-domain nodes on the spine (r - 1 for RM(r, m), r <= 4)
+// Permutation-domain nodes on the spine the layout holds (r - 1 for
+// RM(r, m)): every internal code of length 2^m, except at L = 64 and at
+// L = 32 for N = 512, where three (r <= 4) keep two workgroups per CU.
+constexpr int max_perm(int M, int L) { return (L >= 64 || (L == 32 && M == 9) || M < 6) ? 3 : M - 3; }
 
 __host__ __device__ constexpr int words_of(int s) { return s >= 5 ? (1 << (s - 5)) : 1; }
 __host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
@@ -58,10 +61,11 @@ struct Lay {
     static constexpr int ANC = PM + (M - 2) * 2 * L;    // [M-2][2][L] bytes
     // per permutation-domain node (by its depth on the leftmost spine):
     // kept candidates, their source path and metric
-    static constexpr int SEL = ANC + (M - 2) * 2 * L / 4; // [kMaxPerm][2L] bytes
-    static constexpr int ORIG = SEL + kMaxPerm * 2 * L / 4; // [kMaxPerm][L] bytes
-    static constexpr int PPM = ORIG + kMaxPerm * L / 4;     // [kMaxPerm][L] floats
-    static constexpr int SCR = PPM + kMaxPerm * L;          // 2L floats: the candidates' LM values
+    static constexpr int NPM = max_perm(M, L);
+    static constexpr int SEL = ANC + (M - 2) * 2 * L / 4; // [NPM][2L] bytes
+    static constexpr int ORIG = SEL + NPM * 2 * L / 4;    // [NPM][L] bytes
+    static constexpr int PPM = ORIG + NPM * L / 4;        // [NPM][L] floats
+    static constexpr int SCR = PPM + NPM * L;             // 2L floats: the candidates' LM values
     static constexpr int PM0 = SCR + 2 * L;                 // L floats: the root's input metrics
     static constexpr int SIDX = PM0 + L;                    // L uint16: FHT survivors' index and sign
     static constexpr int PAR = SIDX + L / 2;                // L bytes: SPC parities of the input paths
@@ -79,7 +83,7 @@ struct Lay {
 
     // Every array the kernel indexes ends at or before the next one begins,
     // for the largest index its accessors form (row l < L, element i < 2^s,
-    // level s, side, permutation-domain depth v < kMaxPerm), and the 8-byte
+    // level s, side, permutation-domain depth v < NPM), and the 8-byte
     // accesses of the SPC flip masks are aligned.  Checked for every built
     // shape when the kernel is instantiated.
     static constexpr bool layout_ok()
@@ -96,9 +100,9 @@ struct Lay {
             return false;
         return PM >= XB_END && PM + (M - 2) * 2 * L <= ANC            // [M-2][2][L] floats
                && ANC + (M - 2) * 2 * L / 4 <= SEL                     // [M-2][2][L] bytes
-               && SEL + kMaxPerm * 2 * L / 4 <= ORIG                   // [kMaxPerm][2L] bytes
-               && ORIG + kMaxPerm * L / 4 <= PPM                       // [kMaxPerm][L] bytes
-               && PPM + kMaxPerm * L <= SCR                            // [kMaxPerm][L] floats
+               && SEL + NPM * 2 * L / 4 <= ORIG                        // [NPM][2L] bytes
+               && ORIG + NPM * L / 4 <= PPM                            // [NPM][L] bytes
+               && PPM + NPM * L <= SCR                                 // [NPM][L] floats
                && SCR + 2 * L <= PM0 && PM0 + L <= SIDX                // 2L and L floats
                && SIDX + L / 2 <= PAR && PAR + L / 4 <= SPC            // L uint16, L bytes
                && SPC % 2 == 0 && SPC_ONE % 2 == 0 && (3 * L) % 2 == 0 // flip masks: 8-byte aligned
@@ -708,7 +712,7 @@ __device__ __forceinline__ void big_node(const BigCtx<M, L> &c, const float *pm_
     const int l = c.tid / G, lt = c.tid % G;
     float *ach = c.a(S - 1); // children's LLRs: L rows of h
     constexpr int VP = V >= 0 ? V : 0; // the node's slot among the spine's permutation nodes
-    static_assert(VP < kMaxPerm, "permutation domain deeper than the layout holds");
+    static_assert(VP < Ly::NPM, "permutation domain deeper than the layout holds");
     uint8_t *sel = c.sel(VP);
     uint8_t *orig = c.orig(VP);
     const float *pmL_in = pm_in;

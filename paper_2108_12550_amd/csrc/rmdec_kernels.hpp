@@ -94,5 +94,7 @@ KernelTable kernels_codes_i(); // the rest of m <= 10, L <= 8, by length
 KernelTable kernels_codes_j();
 KernelTable kernels_codes_k();
 KernelTable kernels_codes_l();
+KernelTable kernels_codes_m(); // lists of 16 and 32 paths for the other internal codes
+KernelTable kernels_codes_n();
 
 } // namespace rmdec

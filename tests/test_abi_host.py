@@ -114,7 +114,8 @@ def test_lists_up_to_eight_cover_the_domain():
 
 def test_unbuilt_kernel_reported():
     assert not rmd.rm_supported(10, 1, 8, rmd.RM_PERM_PFHT)
-    assert not rmd.rm_supported(9, 5, 16, rmd.RM_PERM_PFHT)
+    assert not rmd.rm_supported(9, 5, 32, rmd.RM_PERM_PFHT)
+    assert not rmd.rm_supported(5, 2, 16, rmd.RM_PERM_PFHT)
 
 
 def test_create_without_device_fails_cleanly():

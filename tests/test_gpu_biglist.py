@@ -23,9 +23,12 @@ if not torch.cuda.is_available():
 NONE, PFHT, FRESH = rmd.RM_PERM_NONE, rmd.RM_PERM_PFHT, rmd.RM_PERM_FRESH
 THREADS = min(16, os.cpu_count() or 1)
 PM_RTOL = 1e-5
-BUILT = [(8, 2, 16), (8, 2, 32), (8, 2, 64), (8, 3, 16), (8, 3, 32), (8, 3, 64), (8, 4, 16), (8, 4, 32),
-         (8, 4, 64), (9, 2, 16), (9, 2, 32), (9, 2, 64), (9, 3, 16), (9, 3, 32), (9, 3, 64), (9, 4, 16),
-         (9, 4, 32), (9, 4, 64), (7, 2, 16), (7, 3, 16), (6, 2, 16)]
+# every internal code (1 < r < m-1) with 6 <= m <= 10 at L = 16 and 32 (at N = 512
+# and L = 32 only r <= 4: three permutation nodes keep two workgroups per CU),
+# and L = 64 for RM(2..4, 8) and RM(2..4, 9)
+BUILT = ([(m, r, L) for m in range(6, 11) for r in range(2, m - 1) for L in (16, 32)
+          if not (m == 9 and L == 32 and r >= 5)]
+         + [(m, r, 64) for m in (8, 9) for r in (2, 3, 4)])
 
 
 def gpu_decode(m, r, P, L, seed, mode, llr):
@@ -97,7 +100,9 @@ def test_unbuilt_large_list_reported():
     assert rmd.rm_supported(9, 4, 32, PFHT) == 1
     assert rmd.rm_supported(9, 2, 64, PFHT) == 1
     assert rmd.rm_supported(10, 2, 64, PFHT) == 0  # 4*L*N bytes of LLRs exceed the LDS of a workgroup
-    assert rmd.rm_supported(10, 2, 32, PFHT) == 0
+    assert rmd.rm_supported(10, 2, 32, PFHT) == 1
+    assert rmd.rm_supported(9, 5, 32, PFHT) == 0   # four permutation nodes at N = 512, L = 32
+    assert rmd.rm_supported(8, 1, 16, PFHT) == 0   # leaf roots have no large-list kernel
 
 
 def test_table5_rm29_l64_plain_and_permuted():
