@@ -351,6 +351,8 @@ def bench_mixed(args, with_cpu=True):
     log(f"inputs ready in {time.perf_counter() - t0:.1f} s")
     decs = [rmd.Decoder(m, r, P, L, seed=SEED) for m, r, P, L in MIXED_CODES]
     stream = torch.cuda.Stream(device=dev)
+    if args.copy_calibration:
+        copy_calibration(dev, stream)
     mx = rmd.MixedLauncher(max_tiles=4 * n + 16)
 
     def segs(tiles):
