@@ -264,7 +264,8 @@ const KernelEntry *find_kernel(int m, int r, int L)
     const KernelTable tabs[] = {kernels_codes_a(), kernels_codes_b(), kernels_codes_c(), kernels_codes_d(),
                                 kernels_codes_e(), kernels_codes_f(), kernels_codes_g(), kernels_codes_h(),
                                 kernels_codes_i(), kernels_codes_j(), kernels_codes_k(), kernels_codes_l(),
-                                kernels_codes_m(), kernels_codes_n()};
+                                kernels_codes_m(), kernels_codes_n(), kernels_codes_o(), kernels_codes_p(),
+                                kernels_codes_q()};
     for (const KernelTable &t : tabs)
         for (int i = 0; i < t.count; i++)
             if (t.entries[i].m == m && t.entries[i].r == r && t.entries[i].L == L)

@@ -1,17 +1,12 @@
 // Kernel instantiations: lists of 16 and 32 paths for the other internal
-// codes of length 512 and 1024 (one workgroup of 512 threads per frame,
+// codes of length 512 (one workgroup of 512 threads per frame,
 // LDS-resident list).
 #include "rmdec_biglist.hpp"
 
 namespace rmdec {
 namespace {
 const KernelEntry kEntries[] = {
-    big::big_entry<9, 5, 16>(), big::big_entry<9, 6, 16>(), big::big_entry<9, 7, 16>(), big::big_entry<10, 2, 16>(),
-    big::big_entry<10, 2, 32>(), big::big_entry<10, 3, 16>(), big::big_entry<10, 3, 32>(),
-    big::big_entry<10, 4, 16>(), big::big_entry<10, 4, 32>(), big::big_entry<10, 5, 16>(),
-    big::big_entry<10, 5, 32>(), big::big_entry<10, 6, 16>(), big::big_entry<10, 6, 32>(),
-    big::big_entry<10, 7, 16>(), big::big_entry<10, 7, 32>(), big::big_entry<10, 8, 16>(),
-    big::big_entry<10, 8, 32>(),
+    big::big_entry<9, 5, 16>(), big::big_entry<9, 6, 16>(), big::big_entry<9, 7, 16>(),
 };
 } // namespace
 

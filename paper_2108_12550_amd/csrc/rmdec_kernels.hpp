@@ -96,5 +96,8 @@ KernelTable kernels_codes_k();
 KernelTable kernels_codes_l();
 KernelTable kernels_codes_m(); // lists of 16 and 32 paths for the other internal codes
 KernelTable kernels_codes_n();
+KernelTable kernels_codes_o();
+KernelTable kernels_codes_p();
+KernelTable kernels_codes_q();
 
 } // namespace rmdec
