@@ -27,11 +27,12 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
-SOURCES = ["rmdec_inst_o.hip", "rmdec_inst_q.hip", "rmdec_inst_l.hip", "rmdec_inst_p.hip", "rmdec_inst_k.hip",
-           "rmdec_inst_n.hip", "rmdec_inst_m.hip", "rmdec_inst_g.hip", "rmdec_inst_h.hip", "rmdec_inst_j.hip",
-           "rmdec_inst_i.hip", "rmdec_inst_f.hip", "rmdec_inst_e.hip", "rmdec_serve_l8.hip", "rmdec_serve_l4.hip",
-           "rmdec_serve_l1.hip", "rmdec_mixed.hip", "rmdec_inst_a.hip", "rmdec_inst_b.hip", "rmdec_inst_c.hip",
-           "rmdec_inst_d.hip", "rmdec_host.hip", "rmdec_serve.hip", "rmdec_fresh.hip"]
+SOURCES = ["rmdec_inst_t.hip", "rmdec_inst_o.hip", "rmdec_inst_q.hip", "rmdec_inst_l.hip", "rmdec_inst_p.hip",
+           "rmdec_inst_k.hip", "rmdec_inst_n.hip", "rmdec_inst_m.hip", "rmdec_inst_g.hip", "rmdec_inst_h.hip",
+           "rmdec_inst_j.hip", "rmdec_inst_i.hip", "rmdec_inst_f.hip", "rmdec_inst_e.hip", "rmdec_serve_l8.hip",
+           "rmdec_serve_l4.hip", "rmdec_serve_l1.hip", "rmdec_mixed.hip", "rmdec_inst_a.hip", "rmdec_inst_b.hip",
+           "rmdec_inst_c.hip", "rmdec_inst_d.hip", "rmdec_inst_r.hip", "rmdec_inst_s.hip", "rmdec_host.hip",
+           "rmdec_serve.hip", "rmdec_fresh.hip"]
 
 
 def _compile(src: str) -> str:

@@ -29,9 +29,9 @@ namespace big {
 
 constexpr int kThreads = 512;
 // Permutation-domain nodes on the spine the layout holds (r - 1 for
-// RM(r, m)): every internal code of length 2^m, except at L = 64 and at
-// L = 32 for N = 512, where three (r <= 4) keep two workgroups per CU.
-constexpr int max_perm(int M, int L) { return (L >= 64 || (L == 32 && M == 9) || M < 6) ? 3 : M - 3; }
+// RM(r, m)): every internal code of length 2^m, except at L = 64, where
+// three (r <= 4) keep two workgroups per CU.
+constexpr int max_perm(int M, int L) { return (L >= 64 || M < 6) ? 3 : M - 3; }
 
 __host__ __device__ constexpr int words_of(int s) { return s >= 5 ? (1 << (s - 5)) : 1; }
 __host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
@@ -74,7 +74,7 @@ struct Lay {
     static constexpr int SPC = (PAR + L / 4 + 1) & ~1;
     static constexpr int SPC_ONE = 5 * L;
     static constexpr int BEST = SPC + 2 * SPC_ONE; // the frame's best codeword, N bits
-    static constexpr int MISC = BEST + (N / 32 > 0 ? N / 32 : 1);
+    static constexpr int MISC = BEST + words_of(M);
     static constexpr int WORDS = MISC + 4; // best metric, improved flag, winner
     static constexpr int BYTES = WORDS * 4;
 
@@ -107,7 +107,7 @@ struct Lay {
                && SIDX + L / 2 <= PAR && PAR + L / 4 <= SPC            // L uint16, L bytes
                && SPC % 2 == 0 && SPC_ONE % 2 == 0 && (3 * L) % 2 == 0 // flip masks: 8-byte aligned
                && SPC + 2 * SPC_ONE <= BEST                            // two copies of 5L words
-               && BEST + (N / 32 > 0 ? N / 32 : 1) <= MISC && MISC + 4 <= WORDS;
+               && BEST + words_of(M) <= MISC && MISC + 4 <= WORDS;
     }
 };
 
@@ -327,13 +327,13 @@ __device__ __forceinline__ void wave_sort(WaveKeys<NK> &k, int lane)
 // round r, and the winning lanes shift their windows, reloading once fewer
 // than two entries are left in a window but not in the list.  The outputs
 // are then written by lanes 0..L-1 together.
-template <int M, int L, int K>
-__device__ __forceinline__ void select_smallest(const BigCtx<M, L> &c, const float *metric, int mstride, const uint16_t *code,
-                                int cstride, float *out_pm, uint8_t *out_src, uint16_t *out_code)
+template <int L, int K>
+__device__ __forceinline__ void select_smallest(int tid, const float *metric, int mstride, const uint16_t *code, int cstride,
+                                                float *out_pm, uint8_t *out_src, uint16_t *out_code)
 {
     static_assert(L <= kWave, "one lane per list");
-    if (c.tid < kWave) {
-        const int lane = c.tid;
+    if (tid < kWave) {
+        const int lane = tid;
         auto key_at = [&](int j) {
             return (lane < L && j < K) ? ((uint64_t)__float_as_uint(metric[lane * mstride + j]) << 32) |
                                              ((uint64_t)lane << 16) | (uint64_t)j
@@ -388,33 +388,45 @@ __device__ __forceinline__ void select_smallest(const BigCtx<M, L> &c, const flo
 }
 
 // ---------------------------------------------------------------------------
-// FHTL leaf RM(1,S) (Alg. 3, 4)
+// FHTL on a list (Alg. 3 over Alg. 4): L path rows of n = 2^S LLRs, path l's
+// at rows + l n.  Per path: the sum of |alpha| (halving tree), the Hadamard
+// transform in place, and the K = min(L, n) largest |F| (ties to the lower
+// index) as candidates with the metric of Eq. (10) from pm_in[l]; then the L
+// smallest of the L K candidates in the order (metric, path, rank): their
+// metrics, source paths and (index, sign) codes into out_pm, out_anc,
+// out_code, and their codewords into xo ([L][words_of(S)] words).  codes:
+// 16-bit scratch, K entries per path at codes + l cstride.  Path l is served
+// by the G = 512/L threads l G .., lanes of one wave.
 // ---------------------------------------------------------------------------
-template <int M, int L, int S, int SIDE>
-__device__ __forceinline__ void fhtl_leaf(const BigCtx<M, L> &c, const float *pm_in)
+template <int L, int S>
+__device__ __forceinline__ void fht_list(int tid, float *rows, uint16_t *codes, int cstride, const float *pm_in,
+                                         float *out_pm, uint8_t *out_anc, uint16_t *out_code, uint32_t *xo)
 {
-    using Ly = Lay<M, L>;
-    constexpr int n = 1 << S, h = n / 2, K = cmin(L, n), G = Ly::G;
+    constexpr int n = 1 << S, K = cmin(L, n), G = kThreads / L;
     constexpr int E = (n + G - 1) / G; // elements per thread of the path's group
-    static_assert(S < M, "leaf roots are not handled here");
-    const int l = c.tid / G, lt = c.tid % G;
-    float *F = c.a(S) + l * n;
-    float *scr = c.a(S - 1); // [L][h]: the sum of |alpha|
-    // Per path, in the path's own rows only (its G threads are one wave's
-    // lanes, so a wave-level sync orders the steps).
-    // Sum of |alpha|, halving tree
-    for (int i = lt; i < h; i += G)
-        scr[l * h + i] = fabsf(F[i]) + fabsf(F[i + h]);
-    wave_sync();
-    for (int wdt = h / 2; wdt >= 1; wdt /= 2) {
-        for (int i = lt; i < wdt; i += G)
-            scr[l * h + i] = scr[l * h + i] + scr[l * h + i + wdt];
-        wave_sync();
+    constexpr int GA = G < n ? G : n;  // threads of the group that hold elements
+    static_assert(G <= kWave && kWave % G == 0, "a path's threads are lanes of one wave");
+    const int l = tid / G, lt = tid % G;
+    float *F = rows + l * n;
+    // Sum of |alpha|, halving tree: the levels of width >= G within each
+    // thread (element lt + G e), the rest a lane butterfly.
+    float v[E];
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+        const int i = lt + e * G;
+        v[e] = i < n ? fabsf(F[i]) : 0.0f;
     }
+#pragma unroll
+    for (int wd = E / 2; wd >= 1; wd /= 2)
+#pragma unroll
+        for (int e = 0; e < wd; e++)
+            v[e] = v[e] + v[e + wd];
+    const float llr_abs = bfly_sum<GA / 2>(v[0]);
+    wave_sync();
     // FHT, strides 2^{S-1} .. 1
     for (int t = 0; t < S; t++) {
         const int hh = 1 << (S - t - 1);
-        for (int p = lt; p < h; p += G) {
+        for (int p = lt; p < n / 2; p += G) {
             const int i = (p / hh) * 2 * hh + (p % hh);
             const float x = F[i], z = F[i + hh];
             F[i] = z - x;
@@ -429,19 +441,18 @@ __device__ __forceinline__ void fhtl_leaf(const BigCtx<M, L> &c, const float *pm
     for (int e = 0; e < E; e++) {
         const int i = lt + e * G;
         if (i < n) {
-            const float v = F[i];
-            key[e] = ((uint64_t)(__float_as_uint(v) & 0x7FFFFFFFu) << 32) | ((uint64_t)(0xFFFFu - i) << 1) |
-                     (v < 0.0f ? 1u : 0u);
+            const float x = F[i];
+            key[e] = ((uint64_t)(__float_as_uint(x) & 0x7FFFFFFFu) << 32) | ((uint64_t)(0xFFFFu - i) << 1) |
+                     (x < 0.0f ? 1u : 0u);
         } else {
             key[e] = 0;
         }
     }
-    const float llr_abs = scr[l * h];
     const float pml = pm_in[l];
     wave_sync();
     // K passes: the group's largest remaining key
-    float *metric = F;                                   // [K] per path, in the path's own row
-    uint16_t *cidx = (uint16_t *)(c.a(S - 1) + l * h); // [K] index << 1 | sign
+    float *metric = F;                     // [K] per path, in the path's own row
+    uint16_t *cidx = codes + l * cstride; // [K] index << 1 | sign
     // (keys are distinct and above 0, the padding, so exactly one lane holds
     // the group maximum and drops it by equality)
     for (int j = 0; j < K; j++) {
@@ -462,13 +473,12 @@ __device__ __forceinline__ void fhtl_leaf(const BigCtx<M, L> &c, const float *pm
     }
     __syncthreads();
     // merge: the L smallest of the L*K candidates in the order (metric, l, j)
-    select_smallest<M, L, K>(c, c.a(S), n, (const uint16_t *)c.a(S - 1), 2 * h, c.pm(S, SIDE), c.anc(S, SIDE),
-                             c.sidx());
+    select_smallest<L, K>(tid, rows, n, codes, cstride, out_pm, out_anc, out_code);
     // the survivors' codewords: bit j = sign ^ parity(~(i | j))
-    uint32_t *xo = c.xb(S, SIDE);
-    for (int q = c.tid; q < L * words_of(S); q += kThreads) {
-        const int ql = q / words_of(S), wd = q % words_of(S);
-        const uint32_t code = (uint32_t)c.sidx()[ql];
+    constexpr int W = words_of(S);
+    for (int q = tid; q < L * W; q += kThreads) {
+        const int ql = q / W, wd = q % W;
+        const uint32_t code = (uint32_t)out_code[ql];
         const uint32_t idx = code >> 1, sg = code & 1u;
         uint32_t word = 0;
         for (int bt = 0; bt < cmin(32, n); bt++) {
@@ -480,86 +490,37 @@ __device__ __forceinline__ void fhtl_leaf(const BigCtx<M, L> &c, const float *pm
     __syncthreads();
 }
 
-// ---------------------------------------------------------------------------
-// SPCL leaf RM(S-1,S) (Eqs. (2)-(6))
-// ---------------------------------------------------------------------------
+// FHTL leaf RM(1,S) of the tree: its rows are level S, the level below is
+// scratch
 template <int M, int L, int S, int SIDE>
-__device__ __forceinline__ void spcl_leaf(const BigCtx<M, L> &c, const float *pm_in)
+__device__ __forceinline__ void fhtl_leaf(const BigCtx<M, L> &c, const float *pm_in)
 {
-    using Ly = Lay<M, L>;
-    constexpr int n = 1 << S, G = Ly::G, W = words_of(S);
-    constexpr int TAU = cmin(L, n - 1);
-    constexpr int E = (n + G - 1) / G;
-    static_assert(S < M && S >= 3, "SPC leaf inside the tree");
-    const int l = c.tid / G, lt = c.tid % G;
-    const float *al = c.a(S) + l * n;
-    uint32_t *hd = (uint32_t *)c.a(S - 2); // [L][W] hard decisions
-    // hard decisions, Eq. (2)
-    for (int q = c.tid; q < L * W; q += kThreads) {
-        const int ql = q / W, wd = q % W;
-        const float *row = c.a(S) + ql * n;
-        uint32_t word = 0;
-        for (int bt = 0; bt < cmin(32, n); bt++)
-            word |= (row[wd * 32 + bt] < 0.0f ? 1u : 0u) << bt;
-        hd[q] = word;
-    }
-    // least reliable positions: keys |alpha| bits, then the index (ties to the lower index)
-    uint64_t key[E];
-#pragma unroll
-    for (int e = 0; e < E; e++) {
-        const int i = lt + e * G;
-        key[e] = i < n ? (((uint64_t)(__float_as_uint(al[i]) & 0x7FFFFFFFu) << 32) | (uint32_t)i) : kKeyPad;
-    }
-    __syncthreads();
-    if (c.tid < L) {
-        uint32_t p = 0;
-        for (int wd = 0; wd < W; wd++)
-            p ^= (uint32_t)__popc(hd[c.tid * W + wd]);
-        c.par()[c.tid] = (uint8_t)(p & 1u);
-    }
-    float *ao = c.a(S) + l * n;                          // [TAU+1] |alpha| at o_t
-    uint16_t *ord = (uint16_t *)(c.a(S - 1) + l * (n / 2)); // [TAU+1] o_t
-    // (keys are distinct and below the padding, so exactly one lane holds
-    // the group minimum and drops it by equality)
-    for (int t = 0; t <= TAU; t++) {
-        double b = key_d(kKeyPad);
-#pragma unroll
-        for (int e = 0; e < E; e++)
-            b = dmin(b, key_d(key[e]));
-        const uint64_t gb = d_key(bfly_min<G / 2>(b));
-#pragma unroll
-        for (int e = 0; e < E; e++)
-            key[e] = key[e] == gb ? kKeyPad : key[e];
-        if (lt == 0) {
-            ao[t] = __uint_as_float((uint32_t)(gb >> 32));
-            ord[t] = (uint16_t)(gb & 0xFFFFu);
-        }
-    }
-    __syncthreads();
-    // list state: source path, parity, metric, flips (Eq. (3) for the start)
-    auto SP = [&](int b) { return c.i(Ly::SPC + b * Ly::SPC_ONE); };
-    auto CP = [&](int b) { return c.i(Ly::SPC + b * Ly::SPC_ONE + L); };
-    auto CPM = [&](int b) { return c.f(Ly::SPC + b * Ly::SPC_ONE + 2 * L); };
-    auto FL = [&](int b) { return (uint64_t *)c.i(Ly::SPC + b * Ly::SPC_ONE + 3 * L); };
-    if (c.tid < L) {
-        const int q = c.tid;
-        const int p = c.par()[q];
-        SP(0)[q] = q;
-        CP(0)[q] = p;
-        const float a0 = c.a(S)[q * n];
-        CPM(0)[q] = p ? pm_in[q] + a0 : pm_in[q];
-        FL(0)[q] = 0;
-    }
-    __syncthreads();
-    // the TAU rounds in wave 0: the 2L candidates (keep 2q, flip 2q+1) as
-    // keys (metric bits, enumeration position), sorted over the lanes; rank
-    // r < L becomes list entry r.  Metrics are non-negative (the flip adds
-    // |alpha_{o_t}| >= |alpha_{o_0}| before subtracting |alpha_{o_0}|), so
-    // their bit patterns order as the values do.
-    if (c.tid < kWave) {
+    static_assert(S < M, "leaf roots are decoded by rm_bigleaf_kernel");
+    fht_list<L, S>(c.tid, c.a(S), (uint16_t *)c.a(S - 1), 1 << S, pm_in, c.pm(S, SIDE), c.anc(S, SIDE), c.sidx(),
+                   c.xb(S, SIDE));
+}
+
+// The TAU split rounds of the SPC list rule (Eqs. (4), (5)), in wave 0.
+// st: two copies of the list state, 5L words each (source path, parity,
+// metric, then the 64-bit flip masks), the first holding the state before
+// the rounds; ao + p * ostride: path p's |alpha| at o_0 .. o_TAU.  The state
+// after the rounds is left in copy TAU & 1.
+template <int L, int TAU>
+__device__ __forceinline__ void spc_rounds(int tid, int *st, const float *ao, int ostride)
+{
+    auto SP = [&](int b) { return st + b * 5 * L; };
+    auto CP = [&](int b) { return st + b * 5 * L + L; };
+    auto CPM = [&](int b) { return (float *)(st + b * 5 * L + 2 * L); };
+    auto FL = [&](int b) { return (uint64_t *)(st + b * 5 * L + 3 * L); };
+    // Each round: the 2L candidates (keep 2q, flip 2q+1) as keys (metric
+    // bits, enumeration position), sorted over the lanes; rank r < L becomes
+    // list entry r.  Metrics are non-negative (the flip adds |alpha_{o_t}| >=
+    // |alpha_{o_0}| before subtracting |alpha_{o_0}|), so their bit patterns
+    // order as the values do.
+    if (tid < kWave) {
         constexpr int NK = 2 * L;
         constexpr int NR = NK > kWave ? 2 : 1;
-        const int lane = c.tid;
+        const int lane = tid;
         int cur = 0;
         for (int t = 1; t <= TAU; t++) {
             if (t > 1) {
@@ -571,7 +532,7 @@ __device__ __forceinline__ void spcl_leaf(const BigCtx<M, L> &c, const float *pm
                 // the state in the copy the code after the rounds reads.
                 float kv = -__builtin_inff(), fv = __builtin_inff();
                 if (lane < L) {
-                    const float *aos = c.a(S) + SP(cur)[lane] * n;
+                    const float *aos = ao + SP(cur)[lane] * ostride;
                     kv = CPM(cur)[lane];
                     fv = (kv + aos[t]) + (1.0f - 2.0f * (float)CP(cur)[lane]) * aos[0];
                 }
@@ -596,7 +557,7 @@ __device__ __forceinline__ void spcl_leaf(const BigCtx<M, L> &c, const float *pm
                 // half-cleaners sort.
                 const int q = lane;
                 const int sp = SP(cur)[q];
-                const float *aos = c.a(S) + sp * n;
+                const float *aos = ao + sp * ostride;
                 const float cpm = CPM(cur)[q];
                 const float fv = (cpm + aos[t]) + (1.0f - 2.0f * (float)CP(cur)[q]) * aos[0];
                 WaveKeys<kWave> fk, z;
@@ -616,7 +577,7 @@ __device__ __forceinline__ void spcl_leaf(const BigCtx<M, L> &c, const float *pm
                     if (e < 2 * L) {
                         const int q = e >> 1, fl = e & 1;
                         const int sp = SP(cur)[q];
-                        const float *aos = c.a(S) + sp * n;
+                        const float *aos = ao + sp * ostride;
                         const float v =
                             fl ? (CPM(cur)[q] + aos[t]) + (1.0f - 2.0f * (float)CP(cur)[q]) * aos[0] : CPM(cur)[q];
                         key[r] = ((uint64_t)__float_as_uint(v) << 32) | (uint32_t)e;
@@ -642,14 +603,92 @@ __device__ __forceinline__ void spcl_leaf(const BigCtx<M, L> &c, const float *pm
         }
     }
     __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// SPCL on a list (Eqs. (2)-(6)): L path rows of n = 2^S LLRs, path l's at
+// rows + l n.  Hard decisions and parity (into hd, [L][words_of(S)] words,
+// and par, [L] bytes), the TAU + 1 least reliable positions of every path
+// (positions into ord + l ostride, 16-bit; |alpha| there over the first
+// TAU + 1 entries of the row), the TAU split rounds (list state in st: two
+// copies of 5L words at an even word offset), then the survivors' metrics,
+// source paths and codewords into out_pm, out_anc and xo.
+// ---------------------------------------------------------------------------
+template <int L, int S>
+__device__ __forceinline__ void spc_list(int tid, float *rows, uint32_t *hd, uint16_t *ord, int ostride, uint8_t *par,
+                                         int *st, const float *pm_in, float *out_pm, uint8_t *out_anc, uint32_t *xo)
+{
+    constexpr int n = 1 << S, G = kThreads / L, W = words_of(S);
+    constexpr int TAU = cmin(L, n - 1);
+    constexpr int E = (n + G - 1) / G;
+    static_assert(S >= 3 && TAU <= 64, "flip masks of 64 bits");
+    const int l = tid / G, lt = tid % G;
+    const float *al = rows + l * n;
+    // hard decisions, Eq. (2)
+    for (int q = tid; q < L * W; q += kThreads) {
+        const int ql = q / W, wd = q % W;
+        const float *row = rows + ql * n;
+        uint32_t word = 0;
+        for (int bt = 0; bt < cmin(32, n); bt++)
+            word |= (row[wd * 32 + bt] < 0.0f ? 1u : 0u) << bt;
+        hd[q] = word;
+    }
+    // least reliable positions: keys |alpha| bits, then the index (ties to the lower index)
+    uint64_t key[E];
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+        const int i = lt + e * G;
+        key[e] = i < n ? (((uint64_t)(__float_as_uint(al[i]) & 0x7FFFFFFFu) << 32) | (uint32_t)i) : kKeyPad;
+    }
+    __syncthreads();
+    if (tid < L) {
+        uint32_t p = 0;
+        for (int wd = 0; wd < W; wd++)
+            p ^= (uint32_t)__popc(hd[tid * W + wd]);
+        par[tid] = (uint8_t)(p & 1u);
+    }
+    float *ao = rows + l * n;          // [TAU+1] |alpha| at o_t
+    uint16_t *od = ord + l * ostride; // [TAU+1] o_t
+    // (keys are distinct and below the padding, so exactly one lane holds
+    // the group minimum and drops it by equality)
+    for (int t = 0; t <= TAU; t++) {
+        double b = key_d(kKeyPad);
+#pragma unroll
+        for (int e = 0; e < E; e++)
+            b = dmin(b, key_d(key[e]));
+        const uint64_t gb = d_key(bfly_min<G / 2>(b));
+#pragma unroll
+        for (int e = 0; e < E; e++)
+            key[e] = key[e] == gb ? kKeyPad : key[e];
+        if (lt == 0) {
+            ao[t] = __uint_as_float((uint32_t)(gb >> 32));
+            od[t] = (uint16_t)(gb & 0xFFFFu);
+        }
+    }
+    __syncthreads();
+    // list state: source path, parity, metric, flips (Eq. (3) for the start)
+    auto SP = [&](int b) { return st + b * 5 * L; };
+    auto CP = [&](int b) { return st + b * 5 * L + L; };
+    auto CPM = [&](int b) { return (float *)(st + b * 5 * L + 2 * L); };
+    auto FL = [&](int b) { return (uint64_t *)(st + b * 5 * L + 3 * L); };
+    if (tid < L) {
+        const int q = tid;
+        const int p = par[q];
+        SP(0)[q] = q;
+        CP(0)[q] = p;
+        const float a0 = rows[q * n];
+        CPM(0)[q] = p ? pm_in[q] + a0 : pm_in[q];
+        FL(0)[q] = 0;
+    }
+    __syncthreads();
+    spc_rounds<L, TAU>(tid, st, rows, n);
     constexpr int cur = TAU & 1; // the state after the rounds
     // codewords: hard decisions with the kept flips, o_0 set by Eq. (6)
-    uint32_t *xo = c.xb(S, SIDE);
-    for (int q = c.tid; q < L * W; q += kThreads) {
+    for (int q = tid; q < L * W; q += kThreads) {
         const int ql = q / W, wd = q % W;
         const int sp = SP(cur)[ql];
         const uint64_t flips = FL(cur)[ql];
-        const uint16_t *os = (const uint16_t *)(c.a(S - 1) + sp * (n / 2));
+        const uint16_t *os = ord + sp * ostride;
         uint32_t word = hd[sp * W + wd];
         for (int t = 1; t <= TAU; t++)
             if ((flips >> (t - 1)) & 1u) {
@@ -660,16 +699,28 @@ __device__ __forceinline__ void spcl_leaf(const BigCtx<M, L> &c, const float *pm
         const uint32_t o0 = os[0];
         if ((int)(o0 >> 5) == wd) {
             const uint32_t hd0 = (hd[sp * W + wd] >> (o0 & 31)) & 1u;
-            const uint32_t par = ((uint32_t)c.par()[sp] ^ (uint32_t)__popcll(flips) ^ hd0) & 1u;
-            word = (word & ~(1u << (o0 & 31))) | (par << (o0 & 31));
+            const uint32_t pr = ((uint32_t)par[sp] ^ (uint32_t)__popcll(flips) ^ hd0) & 1u;
+            word = (word & ~(1u << (o0 & 31))) | (pr << (o0 & 31));
         }
         xo[q] = word;
     }
-    if (c.tid < L) {
-        c.pm(S, SIDE)[c.tid] = CPM(cur)[c.tid];
-        c.anc(S, SIDE)[c.tid] = (uint8_t)SP(cur)[c.tid];
+    if (tid < L) {
+        out_pm[tid] = CPM(cur)[tid];
+        out_anc[tid] = (uint8_t)SP(cur)[tid];
     }
     __syncthreads();
+}
+
+// SPCL leaf RM(S-1,S) of the tree: its rows are level S, the two levels
+// below are scratch
+template <int M, int L, int S, int SIDE>
+__device__ __forceinline__ void spcl_leaf(const BigCtx<M, L> &c, const float *pm_in)
+{
+    using Ly = Lay<M, L>;
+    static_assert(S < M && S >= 3, "SPC leaf inside the tree");
+    static_assert(Ly::SPC_ONE == 5 * L && Ly::SPC % 2 == 0, "list state layout");
+    spc_list<L, S>(c.tid, c.a(S), (uint32_t *)c.a(S - 2), (uint16_t *)c.a(S - 1), 1 << S, c.par(), c.i(Ly::SPC), pm_in,
+                   c.pm(S, SIDE), c.anc(S, SIDE), c.xb(S, SIDE));
 }
 
 // ---------------------------------------------------------------------------
@@ -873,6 +924,20 @@ __device__ __forceinline__ void big_node(const BigCtx<M, L> &c, const float *pm_
     }
 }
 
+// a frame's codeword (N bits as words_of(M) words in LDS, one partial word
+// below N = 32) to its N/8 output bytes
+template <int N>
+__device__ __forceinline__ void store_codeword(int tid, const uint32_t *x, uint8_t *out)
+{
+    if constexpr (N >= 32) {
+        for (int i = tid; i < N / 32; i += kThreads)
+            ((uint32_t *)out)[i] = x[i];
+    } else {
+        if (tid < N / 8)
+            out[tid] = (uint8_t)(x[0] >> (8 * tid));
+    }
+}
+
 // ---------------------------------------------------------------------------
 // the kernel: one workgroup per frame (grid-stride), P decoders per frame
 // ---------------------------------------------------------------------------
@@ -880,7 +945,7 @@ template <int M, int R, int L>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) rm_biglist_kernel(KernelArgs args)
 {
     using Ly = Lay<M, L>;
-    constexpr int N = 1 << M;
+    constexpr int N = 1 << M, W = words_of(M);
     extern __shared__ __align__(16) uint32_t big_smem[];
     BigCtx<M, L> c;
     c.w = big_smem;
@@ -893,7 +958,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
             c.y()[i] = args.llr[f * N + i];
         if (c.tid == 0)
             misc[0] = __builtin_inff();
-        for (int i = c.tid; i < N / 32; i += kThreads)
+        for (int i = c.tid; i < W; i += kThreads)
             c.w[Ly::BEST + i] = 0u;
         __syncthreads();
         for (int d = 0; d < args.P; d++) {
@@ -922,13 +987,12 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
             if (c.i(Ly::MISC)[1]) {
                 const int ls = c.i(Ly::MISC)[2];
                 const uint32_t *x = c.xb(M, 0);
-                for (int wd = c.tid; wd < N / 32; wd += kThreads)
-                    c.w[Ly::BEST + wd] = x[ls * (N / 32) + wd];
+                for (int wd = c.tid; wd < W; wd += kThreads)
+                    c.w[Ly::BEST + wd] = x[ls * W + wd];
             }
             __syncthreads();
         }
-        for (int i = c.tid; i < N / 32; i += kThreads)
-            ((uint32_t *)(args.out_bits + f * (N / 8)))[i] = c.w[Ly::BEST + i];
+        store_codeword<N>(c.tid, c.w + Ly::BEST, args.out_bits + f * (N / 8));
         if (c.tid == 0 && args.out_pm)
             args.out_pm[f] = misc[0];
         __syncthreads();
@@ -952,6 +1016,175 @@ template <int M, int R, int L>
 constexpr KernelEntry big_entry()
 {
     return KernelEntry{M, R, L, 1, 0, 2 * L + 4 * L * perm_spine(M, R), &launch_big<M, R, L>, Lay<M, L>::BYTES};
+}
+
+// ---------------------------------------------------------------------------
+// Leaf roots: the code is itself RM(1, m) (FHTL) or RM(m-1, m) (SPCL).  Alg. 2
+// starts the L paths from the channel LLRs through the decoder's L initial
+// maps (y itself for every path without permutations, one path active); the
+// leaf's list rule runs on their rows, and the survivor Alg. 5 keeps goes
+// back to channel order through the inverse of its path's initial map.
+// LDS in 32-bit words: the paths' rows and small per-path arrays, no levels
+// below (L N + N + O(L N / 32) words: 134 KB at L = 32, N = 1024).
+// ---------------------------------------------------------------------------
+template <int M, int L>
+struct LeafLay {
+    static constexpr int N = 1 << M;
+    static constexpr int W = words_of(M);   // codeword words per path
+    static constexpr int K = cmin(L, N);    // FHT candidates per path
+    static constexpr int TAU = cmin(L, N - 1); // SPC splits
+    static constexpr int OW = ((K > TAU + 1 ? K : TAU + 1) + 1) / 2; // words per path of 16-bit codes
+    static constexpr int Y = 0;             // N floats: the channel LLRs
+    static constexpr int ROW = N;           // [L][N] floats: the paths' rows
+    static constexpr int HD = ROW + L * N;  // [L][W] SPC hard decisions
+    static constexpr int ORD = HD + L * W;  // [L][OW] FHT (index, sign) codes or SPC positions, 16-bit
+    static constexpr int XB = ORD + L * OW; // [L][W] the survivors' codewords
+    static constexpr int PMO = XB + L * W;  // [L] floats: their metrics
+    static constexpr int ANC = PMO + L;     // [L] bytes: their source paths
+    static constexpr int SIDX = ANC + L / 4; // [L] 16-bit: FHT survivors' codes
+    static constexpr int PAR = SIDX + L / 2; // [L] bytes: SPC parities
+    static constexpr int PM0 = PAR + L / 4;  // [L] floats: the paths' input metrics
+    static constexpr int SPC = (PM0 + L + 1) & ~1; // SPC list state: two copies of 5L words
+    static constexpr int BEST = SPC + 10 * L; // [W] the frame's best codeword
+    static constexpr int MISC = BEST + W;     // best metric, improved flag, winner
+    static constexpr int WORDS = MISC + 4;
+    static constexpr int BYTES = WORDS * 4;
+    static constexpr bool layout_ok()
+    {
+        return L % 4 == 0 && L <= kWave && kThreads / L <= kWave && 2 * OW >= K && 2 * OW >= TAU + 1 &&
+               TAU <= 64 && SPC % 2 == 0 && SPC >= PM0 + L && BEST >= SPC + 10 * L;
+    }
+};
+
+// Waves per SIMD the registers must allow: four (two workgroups per CU)
+// where the LDS allows it; two where one workgroup fills a CU's LDS, which
+// leaves room for 64 register-held keys per thread (L = 32 at N = 1024).
+template <int M, int L>
+constexpr int leaf_wpe()
+{
+    return 2 * LeafLay<M, L>::BYTES <= 160 * 1024 ? 4 : 2;
+}
+
+template <int M, int R, int L, int WPE>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(WPE))) rm_bigleaf_kernel(KernelArgs args)
+{
+    using Ly = LeafLay<M, L>;
+    static_assert(Ly::layout_ok(), "leaf-root LDS layout");
+    static_assert(R == 1 || R == M - 1, "leaf roots only");
+    constexpr int N = 1 << M, W = Ly::W, G = kThreads / L;
+    extern __shared__ __align__(16) uint32_t big_smem[];
+    uint32_t *w = big_smem;
+    const int tid0 = threadIdx.x;
+    float *y = (float *)(w + Ly::Y);
+    float *row = (float *)(w + Ly::ROW);
+    float *pm0 = (float *)(w + Ly::PM0);
+    float *pmo = (float *)(w + Ly::PMO);
+    uint8_t *anc = (uint8_t *)(w + Ly::ANC);
+    float *misc = (float *)(w + Ly::MISC);
+    int *imisc = (int *)(w + Ly::MISC);
+    for (int64_t f = blockIdx.x; f < args.n_frames; f += gridDim.x) {
+        const uint32_t *fmaps = args.maps + f * args.frame_stride;
+        for (int i = tid0; i < N; i += kThreads)
+            y[i] = args.llr[f * N + i];
+        if (tid0 == 0)
+            misc[0] = __builtin_inff();
+        for (int i = tid0; i < W; i += kThreads)
+            w[Ly::BEST + i] = 0u;
+        __syncthreads();
+        for (int d = 0; d < args.P; d++) {
+            // the thread index through an opaque move per decoder: otherwise
+            // the per-element constants derived from it are computed once and
+            // held in registers (spilled) across the frame loop
+            int tid;
+            asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"(tid0));
+            const int l = tid / G, lt = tid % G;
+            const uint32_t *dmaps = fmaps + (size_t)d * args.maps_per_dec * kMapWords;
+            if (tid < L)
+                pm0[tid] = (args.pfht || tid == 0) ? 0.0f : __builtin_inff();
+            // path l's row: y through its initial map (map l)
+            {
+                MapR<M> mp;
+                if (args.pfht)
+                    load_map<M>(dmaps + (size_t)l * kMapWords, mp);
+                else
+                    identity_map<M>(mp);
+                for (int i = lt; i < N; i += G)
+                    row[l * N + i] = y[apply_map<M>(mp, (uint32_t)i)];
+            }
+            __syncthreads();
+            if constexpr (R == 1)
+                fht_list<L, M>(tid, row, (uint16_t *)(w + Ly::ORD), 2 * Ly::OW, pm0, pmo, anc,
+                               (uint16_t *)(w + Ly::SIDX), w + Ly::XB);
+            else
+                spc_list<L, M>(tid, row, w + Ly::HD, (uint16_t *)(w + Ly::ORD), 2 * Ly::OW, (uint8_t *)(w + Ly::PAR),
+                               (int *)(w + Ly::SPC), pm0, pmo, anc, w + Ly::XB);
+            // Alg. 5: first minimum over the list; replace only if strictly smaller
+            if (tid == 0) {
+                int ls = 0;
+                for (int q = 1; q < L; q++)
+                    if (pmo[q] < pmo[ls])
+                        ls = q;
+                const int better = pmo[ls] < misc[0];
+                if (better)
+                    misc[0] = pmo[ls];
+                imisc[1] = better;
+                imisc[2] = ls;
+            }
+            __syncthreads();
+            if (imisc[1]) {
+                // bit j in channel order is bit inv(j) of the survivor's
+                // codeword, inv the inverse of its path's initial map (map
+                // L + path); 64 bits per wave and pass, gathered by a ballot
+                const int ls = imisc[2];
+                MapR<M> inv;
+                if (args.pfht)
+                    load_map<M>(dmaps + (size_t)(L + anc[ls]) * kMapWords, inv);
+                else
+                    identity_map<M>(inv);
+                const uint32_t *x = w + Ly::XB + ls * W;
+                for (int j0 = 0; j0 < N; j0 += kThreads) {
+                    const int j = j0 + tid;
+                    uint32_t bit = 0;
+                    if (j < N) {
+                        const uint32_t s = apply_map<M>(inv, (uint32_t)j);
+                        bit = (x[s >> 5] >> (s & 31)) & 1u;
+                    }
+                    const uint64_t mask = __ballot(bit);
+                    const int base = j0 + (tid & ~(kWave - 1));
+                    if ((tid & (kWave - 1)) == 0 && base < N) {
+                        w[Ly::BEST + base / 32] = (uint32_t)mask;
+                        if (base + 32 < N)
+                            w[Ly::BEST + base / 32 + 1] = (uint32_t)(mask >> 32);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        store_codeword<N>(tid0, w + Ly::BEST, args.out_bits + f * (N / 8));
+        if (tid0 == 0 && args.out_pm)
+            args.out_pm[f] = misc[0];
+        __syncthreads();
+    }
+}
+
+template <int M, int R, int L>
+hipError_t launch_bigleaf(const KernelArgs &args, int blocks, hipStream_t stream)
+{
+    constexpr size_t lds = LeafLay<M, L>::BYTES;
+    constexpr int WPE = leaf_wpe<M, L>();
+    static const hipError_t attr = hipFuncSetAttribute((const void *)&rm_bigleaf_kernel<M, R, L, WPE>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (attr != hipSuccess)
+        return attr;
+    hipLaunchKernelGGL((rm_bigleaf_kernel<M, R, L, WPE>), dim3(blocks), dim3(kThreads), lds, stream, args);
+    return hipGetLastError();
+}
+
+// a leaf root holds its decoder's L initial maps and their inverses
+template <int M, int R, int L>
+constexpr KernelEntry bigleaf_entry()
+{
+    return KernelEntry{M, R, L, 1, 0, 2 * L, &launch_bigleaf<M, R, L>, LeafLay<M, L>::BYTES};
 }
 
 } // namespace big

@@ -76,6 +76,29 @@ hipError_t launch_decoder(const rm_decoder *d, const KernelArgs &a, int64_t n_fr
     const int blocks = (int)(b > (1 << 30) ? (1 << 30) : b);
     return (d->packed ? d->kern->launch_packed : d->kern->launch)(a, blocks, d->stream);
 }
+
+// the tables of the instantiation units rmdec_inst_*.hip
+KernelTable kernels_codes_a();
+KernelTable kernels_codes_b();
+KernelTable kernels_codes_c();
+KernelTable kernels_codes_d();
+KernelTable kernels_codes_e();
+KernelTable kernels_codes_f();
+KernelTable kernels_codes_g(); // lists of 16, 32 and 64 paths
+KernelTable kernels_codes_h(); // lists of 64 paths, N = 512
+KernelTable kernels_codes_i(); // the rest of m <= 10, L <= 8, by length
+KernelTable kernels_codes_j();
+KernelTable kernels_codes_k();
+KernelTable kernels_codes_l();
+KernelTable kernels_codes_m(); // lists of 16 and 32 paths for the other internal codes
+KernelTable kernels_codes_n();
+KernelTable kernels_codes_o();
+KernelTable kernels_codes_p();
+KernelTable kernels_codes_q();
+KernelTable kernels_codes_r(); // leaf roots with lists of 8 to 32 paths
+KernelTable kernels_codes_s();
+KernelTable kernels_codes_t();
+
 } // namespace rmdec
 
 namespace {
@@ -265,7 +288,7 @@ const KernelEntry *find_kernel(int m, int r, int L)
                                 kernels_codes_e(), kernels_codes_f(), kernels_codes_g(), kernels_codes_h(),
                                 kernels_codes_i(), kernels_codes_j(), kernels_codes_k(), kernels_codes_l(),
                                 kernels_codes_m(), kernels_codes_n(), kernels_codes_o(), kernels_codes_p(),
-                                kernels_codes_q()};
+                                kernels_codes_q(), kernels_codes_r(), kernels_codes_s(), kernels_codes_t()};
     for (const KernelTable &t : tabs)
         for (int i = 0; i < t.count; i++)
             if (t.entries[i].m == m && t.entries[i].r == r && t.entries[i].L == L)

@@ -76,28 +76,12 @@ constexpr KernelEntry entry()
                            &launch_decode<M, R, L, D, WPE>};
 }
 
-// Each translation unit rmdec_inst_*.hip defines one table.
+// Each translation unit rmdec_inst_*.hip defines one table (kernels_codes_a
+// .. kernels_codes_t, which rmdec_host.hip searches).
 struct KernelTable {
     const KernelEntry *entries;
     int count;
 };
 
-KernelTable kernels_codes_a();
-KernelTable kernels_codes_b();
-KernelTable kernels_codes_c();
-KernelTable kernels_codes_d();
-KernelTable kernels_codes_e();
-KernelTable kernels_codes_f();
-KernelTable kernels_codes_g(); // lists of 16, 32 and 64 paths
-KernelTable kernels_codes_h(); // lists of 64 paths, N = 512
-KernelTable kernels_codes_i(); // the rest of m <= 10, L <= 8, by length
-KernelTable kernels_codes_j();
-KernelTable kernels_codes_k();
-KernelTable kernels_codes_l();
-KernelTable kernels_codes_m(); // lists of 16 and 32 paths for the other internal codes
-KernelTable kernels_codes_n();
-KernelTable kernels_codes_o();
-KernelTable kernels_codes_p();
-KernelTable kernels_codes_q();
 
 } // namespace rmdec

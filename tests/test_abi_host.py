@@ -103,19 +103,20 @@ def test_kernels_built_for_configs(m, r, L):
     assert rmd.rm_supported(m, r, L, rmd.RM_PERM_PFHT)
 
 
-def test_lists_up_to_eight_cover_the_domain():
-    """Every RM(r, m) with 3 <= m <= 10, 1 <= r <= m-1 is built at L = 1, 2, 4
-    and 8, except the two N = 1024 leaf roots at L = 8 (their register
-    footprint, 256 VGPRs and hundreds spilled, is not built)."""
-    missing = [(m, r, L) for m in range(3, 11) for r in range(1, m) for L in (1, 2, 4, 8)
+def test_kernels_cover_the_domain():
+    """Every RM(r, m) with 3 <= m <= 10, 1 <= r <= m-1 is built at L = 1, 2,
+    4, 8, 16 and 32 (lists of 16 and more, and the two N = 1024 leaf roots at
+    L = 8, run one workgroup of 512 threads per frame)."""
+    missing = [(m, r, L) for m in range(3, 11) for r in range(1, m) for L in (1, 2, 4, 8, 16, 32)
                if not rmd.rm_supported(m, r, L, rmd.RM_PERM_PFHT)]
-    assert missing == [(10, 1, 8), (10, 9, 8)]
+    assert missing == []
 
 
 def test_unbuilt_kernel_reported():
-    assert not rmd.rm_supported(10, 1, 8, rmd.RM_PERM_PFHT)
-    assert not rmd.rm_supported(9, 5, 32, rmd.RM_PERM_PFHT)
-    assert not rmd.rm_supported(5, 2, 16, rmd.RM_PERM_PFHT)
+    # lists of 64 paths: RM(2..4, 8) and RM(2..4, 9) only
+    assert not rmd.rm_supported(10, 2, 64, rmd.RM_PERM_PFHT)
+    assert not rmd.rm_supported(7, 2, 64, rmd.RM_PERM_PFHT)
+    assert not rmd.rm_supported(8, 1, 64, rmd.RM_PERM_PFHT)
 
 
 def test_create_without_device_fails_cleanly():

@@ -23,12 +23,13 @@ if not torch.cuda.is_available():
 NONE, PFHT, FRESH = rmd.RM_PERM_NONE, rmd.RM_PERM_PFHT, rmd.RM_PERM_FRESH
 THREADS = min(16, os.cpu_count() or 1)
 PM_RTOL = 1e-5
-# every internal code (1 < r < m-1) with 6 <= m <= 10 at L = 16 and 32 (at N = 512
-# and L = 32 only r <= 4: three permutation nodes keep two workgroups per CU),
-# and L = 64 for RM(2..4, 8) and RM(2..4, 9)
-BUILT = ([(m, r, L) for m in range(6, 11) for r in range(2, m - 1) for L in (16, 32)
-          if not (m == 9 and L == 32 and r >= 5)]
+# every internal code (1 < r < m-1) with 4 <= m <= 10 at L = 16 and 32, and
+# L = 64 for RM(2..4, 8) and RM(2..4, 9)
+BUILT = ([(m, r, L) for m in range(4, 11) for r in range(2, m - 1) for L in (16, 32)]
          + [(m, r, 64) for m in (8, 9) for r in (2, 3, 4)])
+# leaf roots RM(1, m) and RM(m-1, m) at L = 16 and 32, and at L = 8 for N = 1024
+LEAF = ([(m, r, L) for m in range(3, 11) for r in (1, m - 1) for L in (16, 32)]
+        + [(10, 1, 8), (10, 9, 8)])
 
 
 def gpu_decode(m, r, P, L, seed, mode, llr):
@@ -57,26 +58,29 @@ def check(m, r, P, L, mode, llr, seed):
     assert_parity(gpu_decode(m, r, P, L, seed, mode, llr), od.decode_batch(llr, n_threads=THREADS), label)
 
 
-@pytest.mark.parametrize("m,r,L", BUILT)
+@pytest.mark.parametrize("m,r,L", BUILT + LEAF)
 def test_permuted_large_lists(m, r, L):
     _, llr = synth.frames(m, r, 24, 2.0, seed=700 + m * 10 + r + L)
     check(m, r, 2, L, PFHT, llr, seed=L + r)
 
 
-@pytest.mark.parametrize("m,r,L", [(9, 4, 32), (8, 3, 64), (9, 2, 16), (8, 2, 32), (8, 4, 64), (7, 3, 16)])
+@pytest.mark.parametrize("m,r,L", [(9, 4, 32), (8, 3, 64), (9, 2, 16), (8, 2, 32), (8, 4, 64), (7, 3, 16),
+                                   (4, 2, 32), (8, 1, 16), (10, 9, 32), (3, 2, 32), (10, 1, 8)])
 def test_plain_large_lists(m, r, L):
     """FHT-FSCL-L: one active path at the start, no permutations."""
     _, llr = synth.frames(m, r, 30, 2.5, seed=800 + m * 10 + r + L)
     check(m, r, 1, L, NONE, llr, seed=0)
 
 
-@pytest.mark.parametrize("m,r,P,L", [(9, 4, 2, 32), (8, 3, 1, 64), (9, 2, 3, 16)])
+@pytest.mark.parametrize("m,r,P,L", [(9, 4, 2, 32), (8, 3, 1, 64), (9, 2, 3, 16), (9, 6, 2, 32), (5, 3, 2, 16),
+                                     (10, 1, 2, 32), (6, 5, 3, 16), (10, 9, 1, 8)])
 def test_fresh_large_lists(m, r, P, L):
     _, llr = synth.frames(m, r, 20, 2.0, seed=900 + m * 10 + r + L)
     check(m, r, P, L, FRESH, llr, seed=5)
 
 
-@pytest.mark.parametrize("m,r,L", [(8, 3, 32), (9, 2, 16), (8, 4, 64), (6, 2, 16)])
+@pytest.mark.parametrize("m,r,L", [(8, 3, 32), (9, 2, 16), (8, 4, 64), (6, 2, 16), (4, 2, 32), (9, 7, 32),
+                                   (7, 1, 32), (9, 8, 16), (3, 1, 32), (10, 9, 8)])
 def test_integer_llr_ties_large_lists(m, r, L):
     rng = np.random.default_rng(m * 1000 + L)
     llr = rng.integers(-2, 3, size=(20, 1 << m)).astype(np.float32)
@@ -101,8 +105,35 @@ def test_unbuilt_large_list_reported():
     assert rmd.rm_supported(9, 2, 64, PFHT) == 1
     assert rmd.rm_supported(10, 2, 64, PFHT) == 0  # 4*L*N bytes of LLRs exceed the LDS of a workgroup
     assert rmd.rm_supported(10, 2, 32, PFHT) == 1
-    assert rmd.rm_supported(9, 5, 32, PFHT) == 0   # four permutation nodes at N = 512, L = 32
-    assert rmd.rm_supported(8, 1, 16, PFHT) == 0   # leaf roots have no large-list kernel
+    assert rmd.rm_supported(9, 5, 32, PFHT) == 1
+    assert rmd.rm_supported(8, 1, 16, PFHT) == 1
+    assert rmd.rm_supported(7, 6, 64, PFHT) == 0   # lists of 64 only for RM(2..4, 8) and RM(2..4, 9)
+
+
+def test_noiseless_leaf_roots():
+    """Leaf roots decode a noiseless codeword exactly, with metric 0."""
+    for m, r, L in [(10, 1, 32), (9, 8, 16), (3, 2, 32), (10, 9, 8)]:
+        x, _ = synth.frames(m, r, 8, 3.0, seed=19 + m)
+        llr = (8.0 * (1.0 - 2.0 * x)).astype(np.float32)
+        print(f"case noiseless RM({r},{m}) L={L}", flush=True)
+        bits, pm = gpu_decode(m, r, 2, L, 4, PFHT, llr)
+        assert np.array_equal(synth.unpack_bits(bits, 1 << m), x)
+        assert np.all(pm == 0.0)
+
+
+def test_leaf_root_sampled_launch():
+    """RM(1,10) with L = 32 (one first-order root), 4096 frames in one launch:
+    every output a codeword, sampled frames against the oracle."""
+    n = 4096
+    _, llr = synth.frames(10, 1, n, -3.0, seed=78)
+    print("case sampled RM(1,10) P=2 L=32 n=4096", flush=True)
+    bits, pm = gpu_decode(10, 1, 2, 32, 6, PFHT, llr)
+    h = torch.from_numpy(synth.monomial_table(10, 10 - 1 - 1).astype(np.float32)).cuda()
+    xb = torch.from_numpy(synth.unpack_bits(bits, 1024).astype(np.float32)).cuda()
+    assert int(torch.remainder(xb @ h.T, 2.0).sum().item()) == 0
+    idx = np.sort(np.random.default_rng(8).choice(n, 24, replace=False))
+    od = oracle.OracleDecoder(10, 1, 2, 32, seed=6)
+    assert_parity((bits[idx], pm[idx]), od.decode_batch(llr[idx], n_threads=THREADS), "sampled")
 
 
 def test_table5_rm29_l64_plain_and_permuted():
