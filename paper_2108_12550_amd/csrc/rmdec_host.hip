@@ -485,11 +485,13 @@ rm_decoder *rm_decoder_create_ex(const rm_config *cfg)
     dec->fresh_pending = false;
     dec->d_maps = nullptr;
     if (fresh) {
-        // the tables of up to 16384 frames at a time (enough waves to fill the
-        // chip), at most 512 MiB
+        // the tables of up to 65536 frames at a time, at most 2 GiB: the draw
+        // kernel runs one thread per (frame, decoder), and the more of them a
+        // launch has, the better it hides its latency (RM(2,9) P = 20 L = 4:
+        // 14.5 M frames/s with chunks of 16384, 15.3 M with 65536)
         const int64_t per_frame = (int64_t)P * mpd * kMapWords * sizeof(uint32_t);
-        int64_t chunk = ((int64_t)512 << 20) / per_frame;
-        chunk = chunk < 1 ? 1 : (chunk > 16384 ? 16384 : chunk);
+        int64_t chunk = ((int64_t)2048 << 20) / per_frame;
+        chunk = chunk < 1 ? 1 : (chunk > 65536 ? 65536 : chunk);
         dec->fresh_chunk = chunk;
         dec->table_bytes = (size_t)(chunk * per_frame);
     }

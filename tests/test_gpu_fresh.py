@@ -69,16 +69,17 @@ def test_fresh_parity_integer_ties():
 
 
 def test_fresh_several_chunks():
-    """RM(2,9) with 512 decoders at L = 1: the table buffer holds 2730 frames,
-    so 6000 frames take three chunks, the last one ragged."""
-    _, llr = synth.frames(9, 2, 6000, 2.5, seed=31)
+    """RM(2,9) with 512 decoders at L = 1: the table buffer (2 GiB, 6 maps of
+    48 bytes per decoder) holds 14563 frames, so 32000 frames take three
+    chunks, the last one ragged."""
+    _, llr = synth.frames(9, 2, 32000, 2.5, seed=31)
     dec = rmd.Decoder(9, 2, 512, 1, seed=3, perm_mode=FRESH)
-    assert dec.info()["table_bytes"] == 2730 * 512 * 6 * 64
+    assert dec.info()["table_bytes"] == 14563 * 512 * 6 * 48
     dec.close()
-    print("case fresh RM(2,9) P=512 L=1 n=6000 (sampled)", flush=True)
+    print("case fresh RM(2,9) P=512 L=1 n=32000 (sampled)", flush=True)
     bits, pm = gpu_decode(9, 2, 512, 1, 3, llr)
     od = oracle.OracleDecoder(9, 2, 512, 1, seed=3, perm_mode=oracle.PERM_FRESH)
-    idx = [0, 1, 2729, 2730, 2731, 5459, 5460, 5461, 5999] + list(range(100, 6000, 457))
+    idx = [0, 1, 14562, 14563, 14564, 29125, 29126, 29127, 31999] + list(range(100, 32000, 1999))
     for f in idx:
         x, p = od.decode(llr[f], frame=f)
         assert np.array_equal(synth.unpack_bits(bits[f:f + 1], 512)[0], x), f"frame {f}"
@@ -110,7 +111,7 @@ def test_fresh_rejected_by_fused_and_server_paths():
 
 def test_fresh_full_size_sampled():
     """The benchmark's code and decoder set, 131,072 frames in one call
-    (eight chunks): every output a codeword, sampled frames against the oracle."""
+    (two chunks): every output a codeword, sampled frames against the oracle."""
     n = 131072
     _, llr = synth.frames(9, 2, n, 3.0, seed=41)
     print("case fresh full-size RM(2,9) P=20 L=4 n=131072", flush=True)
@@ -121,7 +122,7 @@ def test_fresh_full_size_sampled():
         assert int(torch.remainder(xb @ h.T, 2.0).sum().item()) == 0
     od = oracle.OracleDecoder(9, 2, 20, 4, seed=0, perm_mode=oracle.PERM_FRESH)
     rng = np.random.default_rng(41)
-    for f in np.sort(rng.choice(n, 40, replace=False)).tolist() + [16383, 16384, n - 1]:
+    for f in np.sort(rng.choice(n, 40, replace=False)).tolist() + [65535, 65536, n - 1]:
         x, p = od.decode(llr[f], frame=f)
         assert np.array_equal(synth.unpack_bits(bits[f:f + 1], 512)[0], x), f"frame {f}"
         assert abs(pm[f] - p) <= PM_RTOL * max(1.0, abs(p)), f"frame {f}"
@@ -133,9 +134,9 @@ def test_fresh_two_streams_in_flight():
     the first call's decode, which still reads the shared table buffer.
     Each result equals the same call made alone."""
     m, r, P, L = 9, 2, 20, 4
-    _, a = synth.frames(m, r, 40000, 2.5, seed=91)  # three table chunks
+    _, a = synth.frames(m, r, 150000, 2.5, seed=91)  # three table chunks
     _, b = synth.frames(m, r, 20000, 2.5, seed=92)
-    print("case fresh two streams RM(2,9) P=20 L=4 n=40000+20000", flush=True)
+    print("case fresh two streams RM(2,9) P=20 L=4 n=150000+20000", flush=True)
     ta, tb = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
     dec = rmd.Decoder(m, r, P, L, seed=4, perm_mode=FRESH)
     s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
@@ -153,7 +154,7 @@ def test_fresh_two_streams_in_flight():
     assert np.array_equal(got_b[0], rb_[0].cpu().numpy()) and np.array_equal(got_b[1], rb_[1].cpu().numpy())
     # and a sample of each against the oracle
     od = oracle.OracleDecoder(m, r, P, L, seed=4, perm_mode=oracle.PERM_FRESH)
-    for f in (0, 16383, 16384, 39999):
+    for f in (0, 65535, 65536, 131072, 149999):
         x, p = od.decode(a[f], frame=f)
         assert np.array_equal(synth.pack_bits(x), got_a[0][f])
     for f in (0, 19999):
