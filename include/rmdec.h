@@ -140,7 +140,10 @@ int rm_perm_tables(int m, int r, int P, int L, uint64_t seed, int perm_mode, uin
 int rm_perm_tables_frame(int m, int r, int P, int L, uint64_t seed, int perm_mode, int64_t frame, uint16_t *rows,
                          uint16_t *b, int *mdim, int cap);
 
-/* 1 if a kernel is built for (m, r, L, perm_mode), else 0.  Host only. */
+/* 1 if a kernel is built for (m, r, L, perm_mode), else 0.  Host only.
+ * Built: every 3 <= m <= 10, 1 <= r <= m-1 at L = 1, 2, 4, 8, 16 and 32 (lists
+ * of 16 and 32, and RM(1,10) and RM(9,10) at L = 8, run one workgroup of 512
+ * threads per frame), and L = 64 for RM(2..4, 8) and RM(2..4, 9). */
 int rm_supported(int m, int r, int L, int perm_mode);
 
 /*
