@@ -92,6 +92,15 @@ def test_all_zero_llr_large_list():
     check(8, 3, 2, 32, PFHT, np.zeros((4, 256), np.float32), seed=2)
 
 
+@pytest.mark.parametrize("m,r,L", [(8, 1, 32), (8, 7, 16), (4, 3, 32), (10, 9, 8)])
+def test_all_zero_llr_leaf_roots(m, r, L):
+    """Every candidate ties: the leaf-root kernel's order of paths and
+    candidates decides the output alone."""
+    llr = np.zeros((4, 1 << m), np.float32)
+    check(m, r, 2, L, PFHT, llr, seed=2)
+    check(m, r, 1, L, NONE, llr, seed=0)
+
+
 def test_noiseless_large_list():
     x, _ = synth.frames(9, 4, 16, 3.0, seed=9)
     llr = (8.0 * (1.0 - 2.0 * x)).astype(np.float32)
