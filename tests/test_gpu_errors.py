@@ -19,6 +19,9 @@ paper's curve.
   while the M = 1 curves agree within 5%; the check there is a factor-2
   band, which any reading error of the permutation domain (no maps, the
   smallest LM kept, M = 1) misses by orders of magnitude.
+* FHT-FSCL-1 on RM(3,9) and RM(4,9) against the k/9999 counts Fig. 5(b) and
+  5(c) print, and lists of 2 to 8 paths on RM(2,9), RM(3,9) and RM(4,9),
+  plain and permuted, against Fig. 5(a)-(c) (measured ratios 0.86-1.12).
 * The large-list decoders (L = 16 and 32) against Fig. 5(a) and 5(c), by
   the same log-ratio test (measured ratios 0.77-1.31; one point left out,
   FHT-FSCL-32 on RM(4,9) at 4.0 dB, where the GPU's 3.1e-4 over 2^20 frames
@@ -225,4 +228,56 @@ def test_large_list_fer_matches_fig5(key, m, r, name, mode, L, ebn0, n):
     dec.close()
     z = log_ratio_z(max(err, 1), n, pub)
     print(f"  {name} RM({r},{m}) {ebn0} dB: GPU {err / n:.3e} ({err}/{n}), Fig. 5 {pub:.3e}; z {z:.2f}", flush=True)
+    assert z <= 3.29
+
+
+def gpu_fer_seeded(m, r, L, mode, ebn0, n, seed0):
+    dec = rmd.Decoder(m, r, 1, L, seed=0, perm_mode=mode)
+    err = 0
+    for b in range(n // FER_BATCH):
+        x, llr = synth.frames(m, r, FER_BATCH, ebn0, seed=seed0 + 37 * b + L + 10 * r)
+        bits, _ = gpu_decode(dec, torch.from_numpy(llr).cuda())
+        err += int(np.any(synth.unpack_bits(bits, 1 << m) != x, axis=1).sum())
+    dec.close()
+    return err
+
+
+@pytest.mark.parametrize("key,r,ebn0,n", [
+    ("fer_rm39", 3, "3.0", 1 << 18), ("fer_rm39", 3, "4.0", 1 << 18),
+    ("fer_rm49", 4, "3.0", 1 << 18), ("fer_rm49", 4, "4.0", 1 << 18),
+])
+def test_plain_fht_fsc_fer_higher_orders_match_fig5_counts(key, r, ebn0, n):
+    """FHT-FSCL-1 on RM(3,9) and RM(4,9) (Fig. 5(b), 5(c)): the printed FER
+    is a count out of 9999; two-proportion z within 3.29."""
+    pub = GOLDEN[key]["FHT-FSCL-1"][ebn0]
+    k_pub = round(pub * 9999)
+    assert abs(k_pub / 9999 - pub) < 1e-7
+    e = gpu_fer_seeded(9, r, 1, rmd.RM_PERM_NONE, float(ebn0), n, 9300)
+    z = two_proportion_z(e, n, k_pub, 9999)
+    print(f"  FHT-FSCL-1 RM({r},9) {ebn0} dB: GPU {e / n:.4e} ({e}/{n}), Fig. 5 {k_pub}/9999; z {z:.2f}", flush=True)
+    assert z <= 3.29
+
+
+@pytest.mark.parametrize("key,r,name,mode,L,ebn0,n", [
+    ("fer_rm39", 3, "FHT-FSCL-8", "none", 8, "3.5", 1 << 18),
+    ("fer_rm39", 3, "p-FHT-FSC-2", "pfht", 2, "3.5", 1 << 18),
+    ("fer_rm39", 3, "p-FHT-FSCL-4", "pfht", 4, "3.0", 1 << 18),
+    ("fer_rm39", 3, "p-FHT-FSCL-8", "pfht", 8, "3.0", 1 << 19),
+    ("fer_rm49", 4, "FHT-FSCL-8", "none", 8, "4.0", 1 << 18),
+    ("fer_rm49", 4, "p-FHT-FSC-2", "pfht", 2, "4.0", 1 << 18),
+    ("fer_rm49", 4, "p-FHT-FSCL-4", "pfht", 4, "3.5", 1 << 18),
+    ("fer_rm49", 4, "p-FHT-FSCL-8", "pfht", 8, "3.5", 1 << 19),
+    ("fer_rm29", 2, "p-FHT-FSCL-8", "pfht", 8, "2.5", 1 << 18),
+    ("fer_rm29", 2, "p-FHT-FSCL-8", "pfht", 8, "3.0", 1 << 20),
+    ("fer_rm29", 2, "p-FHT-FSC-2", "pfht", 2, "3.5", 1 << 18),
+])
+def test_list_fer_higher_orders_match_fig5(key, r, name, mode, L, ebn0, n):
+    """One decoder with lists of 2 to 8 paths on RM(2,9), RM(3,9) and RM(4,9)
+    (Fig. 5(a)-(c)), plain and permuted: log-ratio z within 3.29, the printed
+    value taken to rest on 100 errors."""
+    pub = GOLDEN[key][name][ebn0]
+    pm = rmd.RM_PERM_NONE if mode == "none" else rmd.RM_PERM_PFHT
+    e = gpu_fer_seeded(9, r, L, pm, float(ebn0), n, 9300)
+    z = log_ratio_z(max(e, 1), n, pub)
+    print(f"  {name} RM({r},9) {ebn0} dB: GPU {e / n:.3e} ({e}/{n}), Fig. 5 {pub:.3e}; z {z:.2f}", flush=True)
     assert z <= 3.29
