@@ -289,13 +289,14 @@ FIG7_CASES = [
     (8, 2, "p-FHT-FSCL-16", 1, 16), (8, 2, "p-FHT-FSCL-1-25", 25, 1), (8, 2, "p-FHT-FSCL-4-5", 5, 4),
     (8, 3, "p-FHT-FSCL-64", 1, 64), (8, 3, "p-FHT-FSCL-1-100", 100, 1), (8, 3, "p-FHT-FSCL-4-16", 16, 4),
     (8, 4, "p-FHT-FSCL-64", 1, 64), (8, 4, "p-FHT-FSCL-1-80", 80, 1), (8, 4, "p-FHT-FSCL-4-16", 16, 4),
+    (9, 2, "p-FHT-FSCL-1-100", 100, 1), (9, 2, "p-FHT-FSCL-64", 1, 64),
 ]
 
 
 @pytest.mark.parametrize("m,r,name,P,L", FIG7_CASES)
 def test_table5_decoders_fer_match_fig7(m, r, name, P, L):
-    """Table 5's decoders on RM(2,8), RM(3,8), RM(4,8) (P decoders of list
-    size L; L = 64 in one workgroup per frame) against Fig. 7(a)-(c) at the
+    """Table 5's decoders on RM(2,8), RM(3,8), RM(4,8) and RM(2,9) (P decoders
+    of list size L; L = 64 in one workgroup per frame) against Fig. 7 at the
     two middle Eb/N0 points of each panel: log-ratio z within 3.29, the
     printed value taken to rest on 100 errors (measured ratios 0.79-1.07)."""
     pubs = GOLDEN["fer_fig7"][f"RM({r},{m})"][name]
